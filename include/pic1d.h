@@ -1,0 +1,237 @@
+/*
+ * pic1d.h -- C ABI of the MI355X (gfx950) library for the 1D particle-in-cell
+ * hot path of RICS-driven pair cascades on dipole field lines.
+ *
+ * What is computed (paper: Mahlmann, Philippov, Soudais, Beloborodov and
+ * Sironi, "1D PIC Simulations of Resonant Scattering-Driven Pair Cascades in
+ * Magnetar Magnetospheres"):
+ *   - field-line geometry B(s), mu(s), r(s) of a dipole line (Appendix B.2);
+ *   - per step, for every particle: field gather, the RICS drag force by
+ *     Strang splitting with the drag limiter, implicit midpoint and damping
+ *     branches (Sec. 3, Eq. implicit), or a stochastic scattering event with
+ *     probability Ndot dt (Sec. 3) and recoil (Appendix A), the Lorentz push,
+ *     the move, a charge-conserving current deposit, absorption at the
+ *     conducting stellar surface (Sec. 3);
+ *   - conversion of photons with E >= 2 m_e c^2 into e-/e+ pairs, limited by
+ *     n_max (Sec. 3), and refill of the surface atmosphere (Appendix B.1);
+ *   - Ampere's law with the static twist current, dE/dt = 4 pi (j_ext - j) (Sec. 3).
+ *
+ * Code units: one cell, one step; c = cfl cells/step; n0 = ppc0 macro-particles
+ * per cell per species; skin depth d0_cells at n0.  Positions are an int32 cell
+ * index plus a float32 offset in [0,1); momenta u = gamma*beta are float32; the
+ * field E and the diagnostics are float64.
+ *
+ * Conventions common to all calls:
+ *   - Every function returns a pic1d_status (0 = PIC1D_OK) unless noted.
+ *   - Pointers documented as "host" point to caller-owned host memory that is
+ *     read or written during the call only.  Pointers documented as "device"
+ *     point to device memory of the current HIP device (e.g. torch tensors).
+ *   - All device work is enqueued on the hipStream_t given in the config;
+ *     calls that return data to host buffers synchronise that stream.
+ *   - One state handle must not be used from two threads at once.
+ *   - After PIC1D_ECAPACITY or PIC1D_ENONFINITE the state is frozen: further
+ *     pic1d_step calls return PIC1D_ESTATE; moments and particles stay readable
+ *     but reflect the partially completed step in which the error occurred.
+ */
+#ifndef PIC1D_H
+#define PIC1D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIC1D_OK = 0,
+    PIC1D_EINVAL = -1,      /* invalid argument or config                      */
+    PIC1D_ENOMEM = -2,      /* workspace too small                             */
+    PIC1D_ECAPACITY = -3,   /* a species of a line ran out of particle slots   */
+    PIC1D_EDEVICE = -4,     /* a HIP runtime call failed                       */
+    PIC1D_ENONFINITE = -5,  /* a momentum or field value became NaN/Inf        */
+    PIC1D_ESTATE = -6       /* state frozen by an earlier error                */
+} pic1d_status;
+
+/* RICS backends: how F_hat, Ndot_hat are evaluated (photon energy is always
+ * the closed form of Appendix A.3, Eq. perpemit). */
+enum { PIC1D_RICS_OFF = 0,     /* no radiation reaction                          */
+       PIC1D_RICS_EXACT = 1,   /* closed forms of Eqs. scatteringNdot, contdrag  */
+       PIC1D_RICS_TABLE = 2,   /* bilinear (log10 gamma, s) table of the same    */
+       PIC1D_RICS_MLP = 3 };   /* the trained surrogate network (pic1d_mlp_*)    */
+
+/* Where a photon with E >= 2 m_e c^2 converts. */
+enum { PIC1D_CONV_IMMEDIATE = 0,   /* at the emission point (Sec. 3)              */
+       PIC1D_CONV_CURVATURE = 1 }; /* where its angle to the curved line reaches
+                                      arcsin(2 m_e c^2 / E): s' = s +- R_curv asin */
+
+/* Initial pair plasma of a line (Sec. 3: homogeneous e-/e+ plasma). */
+enum { PIC1D_INIT_COLD = 0,    /* u = 0                                          */
+       PIC1D_INIT_HOT = 1,     /* gamma log-uniform in [1, init_gamma_max], random sign */
+       PIC1D_INIT_STREAM = 2,  /* e+ at +gamma*init_beta, e- opposite (along j)  */
+       PIC1D_INIT_EMPTY = 3 }; /* no particles                                   */
+
+/* Species index. */
+enum { PIC1D_E_PAIR = 0, PIC1D_P_PAIR = 1, PIC1D_E_ATM = 2, PIC1D_ION = 3, PIC1D_NSPECIES = 4 };
+
+/* Moment flags. */
+enum { PIC1D_MOM_INSTANT = 0, PIC1D_MOM_AVERAGE = 1, PIC1D_MOM_RESET = 2 };
+
+/* Counter slots of pic1d_moments.counters. */
+enum { PIC1D_CNT_EVENTS = 0,          /* stochastic RICS events                 */
+       PIC1D_CNT_PAIRS = 1,           /* e-/e+ pairs created                    */
+       PIC1D_CNT_ESCAPED = 2,         /* photons that did not convert           */
+       PIC1D_CNT_ABSORBED = 3,        /* particles absorbed by the walls        */
+       PIC1D_CNT_PSC_CLIPPED = 4,     /* event probabilities Ndot*dt clipped at 1 */
+       PIC1D_CNT_LIMITED = 5,         /* drag half steps taken by the damping branch */
+       PIC1D_CNT_NEWTON = 6,          /* drag half steps that needed Newton iterations */
+       PIC1D_CNT_ATM = 7,             /* atmosphere (e-, ion) pairs injected    */
+       PIC1D_CNT_PUSHED = 8,          /* particle-steps pushed                  */
+       PIC1D_CNT_DRAWS = 9,           /* Philox draws of event decisions        */
+       PIC1D_NCOUNTERS = 16 };
+
+typedef struct {
+    double r_eq;              /* equatorial radius of the line, R_max / R*   */
+    int32_t n_cells;          /* cells, uniform in arc length (>= 2)         */
+    int32_t ppc_init;         /* initial e-/e+ pairs per cell (>= 0)         */
+    int32_t init_mode;        /* PIC1D_INIT_*                                */
+    int32_t pad0;
+    double init_gamma_max;    /* HOT: upper end of the gamma range           */
+    double init_beta;         /* STREAM: |beta| of both species (< 1)        */
+    int64_t capacity[4];      /* particle slots per species; 0 = default     */
+} pic1d_line;
+
+typedef struct {
+    int32_t n_lines;          /* >= 1 field lines, advanced together         */
+    int32_t pad0;
+    const pic1d_line* lines;  /* host, n_lines entries                       */
+    double b_pole;            /* B_star / B_QED at the pole surface (10)     */
+    double cfl;               /* c0/c (0.5), cells per step at c             */
+    double d0_cells;          /* cells per skin depth at n0 (48)             */
+    double ppc0;              /* macro-particles per cell per species at n0  */
+    double j_twist;           /* j_psi / (n0 e c), signed along +s           */
+    double kT_keV;            /* photon temperature                          */
+    double eta_min;           /* eta_min prefactor: tau_min w_p0 = eta_min (n_psi/n0)^(1/2) */
+    double b_thr;             /* stochastic regime where b >= b_thr (0.1)    */
+    double mass_ratio;        /* m_i / m_e                                   */
+    int32_t rics_backend;     /* PIC1D_RICS_*                                */
+    int32_t table_nlg;        /* TABLE: nodes in log10 gamma over [0, 8]     */
+    int32_t table_ns;         /* TABLE: nodes in s                           */
+    int32_t pairs;            /* 1: photons with E >= 2 m_e c^2 make pairs   */
+    int32_t conversion;       /* PIC1D_CONV_*                                */
+    int32_t atmosphere;       /* 1: refill the surface layers (Appendix B.1) */
+    int32_t gravity;          /* 1: gravity T/h towards the wall in the layer */
+    int32_t frozen_field;     /* 1: skip Ampere (test mode)                  */
+    double nmax_over_n0;      /* n_max/n0 per cell, all species; <= 0: d0_cells^2 */
+    double atm_a0;            /* peak atmosphere density / n0; <= 0: 18 |j_twist| */
+    double atm_h_cells;       /* scale height in cells; <= 0: 3 d0 / a0^(1/2) */
+    double atm_T;             /* atmosphere temperature / m_e c^2 (0.01)     */
+    double atm_cut;           /* layer where a0 exp(-d/h) >= atm_cut (0.01)  */
+    uint64_t seed;            /* Philox key                                  */
+    int32_t sort_interval;    /* steps between cell sorts; 0 = never         */
+    int32_t avg_start_step;   /* accumulate averages from this step; < 0 off */
+    const void* mlp_weights;  /* MLP backend: host, packed fp32 weights (pic1d_mlp_param_count floats) */
+    void* workspace;          /* device, >= pic1d_workspace_size bytes, 256-B aligned */
+    size_t workspace_bytes;
+    void* stream;             /* hipStream_t all work is enqueued on          */
+} pic1d_config;
+
+typedef struct {
+    /* caller-owned host arrays; any may be NULL to skip it.  Sizes for a line
+     * of n cells: n_cell[s] n, j n, E n, pair_rate n. */
+    double* n_cell[4];        /* density per cell in units of n0, per species */
+    double* j;                /* plasma current on cell centres, units n0 e c */
+    double* E;                /* E on cell centres, code units                 */
+    double* pair_rate;        /* pairs created per cell per step               */
+    /* scalars always filled */
+    double gauss_residual;    /* max_i |E_{i+1/2}-E_{i-1/2}-4 pi rho_i| / (4 pi Q ppc0), interior nodes */
+    double v_circuit;         /* e V_c / m_e c^2 = -(1/c^2) sum_k E_k         */
+    double energy_kinetic;    /* sum m c^2 (gamma - 1), code units            */
+    double energy_field;      /* sum E^2 / 8 pi, code units                   */
+    int64_t count[4];         /* live particles per species                   */
+    int64_t counters[16];     /* PIC1D_CNT_* since init (slots 10-15 reserved) */
+    int64_t step;             /* steps taken since init                       */
+    int64_t avg_steps;        /* steps in the averages                        */
+} pic1d_moments_out;
+
+typedef struct pic1d_state pic1d_state;
+
+/* Bytes of device workspace needed by cfg (cfg->workspace may be NULL).
+ * Errors: EINVAL for an invalid config. */
+int pic1d_workspace_size(const pic1d_config* cfg, size_t* bytes);
+
+/* Build the state: geometry node tables and RICS tables on the host in FP64
+ * (Appendix B.2), carve cfg->workspace, upload, and create the initial plasma
+ * (Philox-uniform offsets, stratified ppc_init per cell).  cfg and the arrays
+ * it points to are copied; the workspace stays owned by the caller and must
+ * outlive the state.  *out receives the handle (NULL on error).
+ * Errors: EINVAL (config), ENOMEM (workspace too small), EDEVICE. */
+int pic1d_init(const pic1d_config* cfg, pic1d_state** out);
+
+/* Advance all lines by n_steps >= 0 steps; enqueues the work and returns after
+ * checking the device error word of the completed steps (this synchronises
+ * the stream once per call).
+ * Errors: ECAPACITY, ENONFINITE (state frozen), ESTATE, EDEVICE. */
+int pic1d_step(pic1d_state* st, int32_t n_steps);
+
+/* Diagnostics of one line: densities, current, field, pair rate (instantaneous
+ * or time-averaged since avg_start_step / the last RESET), Gauss residual
+ * computed on the device in FP64 from cloud-in-cell charge, circuit potential,
+ * energies, counts and counters.  flags: PIC1D_MOM_INSTANT or _AVERAGE, plus
+ * PIC1D_MOM_RESET to restart the averages after reading.
+ * Errors: EINVAL (line out of range), EDEVICE. */
+int pic1d_moments(pic1d_state* st, int32_t line, int32_t flags, pic1d_moments_out* out);
+
+/* Release the state (not the workspace).  NULL is a no-op. */
+void pic1d_free(pic1d_state* st);
+
+/* Text of the last error on st (or of the last failed init when st is NULL);
+ * valid until the next call on the same handle. */
+const char* pic1d_last_error(const pic1d_state* st);
+
+/* Copy the live particles of one species of one line to host arrays of
+ * `capacity` entries (cell, offset, u, id); *count receives the number of live
+ * particles (EINVAL and nothing copied if it exceeds capacity).  The order is
+ * the library's storage order, which carries no meaning. */
+int pic1d_get_particles(pic1d_state* st, int32_t line, int32_t species, int64_t capacity,
+                        int64_t* count, int32_t* cell, float* offset, float* u, uint64_t* id);
+
+/* Replace one species of one line by `count` particles from host arrays.
+ * cell in [0, n_cells), offset in [0, 1).  Errors: EINVAL, ECAPACITY. */
+int pic1d_set_particles(pic1d_state* st, int32_t line, int32_t species, int64_t count,
+                        const int32_t* cell, const float* offset, const float* u,
+                        const uint64_t* id);
+
+/* Copy E of one line (n_cells doubles) to / from host memory. */
+int pic1d_get_field(pic1d_state* st, int32_t line, double* E);
+int pic1d_set_field(pic1d_state* st, int32_t line, const double* E);
+
+/* Set the step counter (keys the Philox draws); for restoring saved states. */
+int pic1d_set_step(pic1d_state* st, int64_t step);
+
+/* Per-kernel timing with HIP events.  pic1d_profile(st, 1) resets the totals
+ * and records an event pair around every kernel that pic1d_step launches from
+ * then on; pic1d_profile(st, 0) stops.  pic1d_profile_read fills out->ms[k]
+ * (total milliseconds) and out->launches[k] for k = PIC1D_KERNEL_*. */
+enum { PIC1D_KERNEL_PUSH = 0, PIC1D_KERNEL_ATMOSPHERE = 1, PIC1D_KERNEL_FIELD = 2, PIC1D_KERNEL_PLAN = 3,
+       PIC1D_KERNEL_SORT = 4, PIC1D_NKERNELS = 8 };
+typedef struct {
+    double ms[8];
+    int64_t launches[8];
+} pic1d_profile_out;
+int pic1d_profile(pic1d_state* st, int32_t enable);
+int pic1d_profile_read(pic1d_state* st, pic1d_profile_out* out);
+
+/* Evaluate the configured RICS backend of one line at n points, exactly as
+ * the pusher does (float32): device arrays s_cells[n] (arc length in cells,
+ * geometry interpolated from the nodes) and u[n]; outputs device arrays
+ * F[n] (F_hat), ndot[n] (Ndot_hat), eps[n] (photon energy / m_e c^2).
+ * Errors: EINVAL. */
+int pic1d_rics_eval(pic1d_state* st, int32_t line, int64_t n, const float* s_cells,
+                    const float* u, float* F, float* ndot, float* eps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC1D_H */

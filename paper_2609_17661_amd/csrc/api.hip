@@ -1,0 +1,698 @@
+// C ABI of the pic1d library (include/pic1d.h): state, workspace carving,
+// kernel launches.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/pic1d.h"
+#include "kernels.h"
+#include "setup.h"
+
+using namespace pic1d;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    bool dry;
+    explicit Carver(void* b) : base((char*)b), dry(b == nullptr) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = dry ? nullptr : (T*)(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Layout {
+    int n_lines = 0, nseg = 0;
+    int64_t total_slots = 0;
+    int32_t n_cells = 0, n_nodes = 0, max_nodes = 0;
+    int64_t table_floats = 0;
+    int32_t n_layer = 0;
+};
+
+}  // namespace
+
+struct pic1d_state {
+    pic1d_config cfg;
+    std::vector<pic1d_line> lines_cfg;
+    std::vector<LineHost> lines;
+    Layout lay;
+    hipStream_t stream = nullptr;
+    int backend = 0;
+    int n_cu = 0, push_blocks = 0, aux_blocks = 0;
+    int frozen = 0;
+    uint64_t host_step = 0;
+    std::string err;
+    std::vector<int64_t> seg_base_h;
+    std::vector<int32_t> seg_cap_h;
+    // device pointers
+    int32_t *cell[2] = {nullptr, nullptr};
+    float *off[2] = {nullptr, nullptr}, *u[2] = {nullptr, nullptr};
+    uint64_t* id[2] = {nullptr, nullptr};
+    int cur = 0;  // which particle buffer set is live
+    int64_t* seg_base = nullptr;
+    int32_t *seg_cap = nullptr, *n_cur = nullptr, *alloc = nullptr, *tile_prefix = nullptr, *new_count = nullptr;
+    LineDev* dlines = nullptr;
+    double *E = nullptr, *j_last = nullptr, *E_sum = nullptr, *j_sum = nullptr;
+    unsigned long long* J = nullptr;
+    int32_t* hist[2] = {nullptr, nullptr};
+    int32_t *pair_step = nullptr, *pair_last = nullptr, *cursor = nullptr, *cell_line = nullptr;
+    long long *pair_sum = nullptr, *n_sum = nullptr, *avg_count = nullptr;
+    float4* nodes = nullptr;
+    double* rc_nodes = nullptr;
+    float* table = nullptr;
+    int32_t *layer_cell = nullptr, *layer_line = nullptr, *layer_target = nullptr;
+    unsigned long long* counters = nullptr;
+    DevScalars* sc = nullptr;
+    unsigned long long* rho = nullptr;
+    double* mom_out = nullptr;
+    // per-kernel event timing (pic1d_profile)
+    int prof_on = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_kernel;     // kernel id of each recorded pair (pool index 2k, 2k+1)
+    double prof_ms[8] = {0};
+    int64_t prof_n[8] = {0};
+    ~pic1d_state() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+int fail(pic1d_state* st, int code, const std::string& msg) {
+    if (st) st->err = msg; else g_init_error = msg;
+    return code;
+}
+
+// Synchronous copy ordered on the state's stream.
+hipError_t copy_sync(hipStream_t s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+#define HIP_TRY(st, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail((st), PIC1D_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+Layout plan_layout(const pic1d_config* c, std::vector<LineHost>* lines_out) {
+    Layout L;
+    L.n_lines = c->n_lines;
+    L.nseg = 4 * c->n_lines;
+    int32_t cb = 0;
+    int64_t toff = 0;
+    for (int l = 0; l < c->n_lines; ++l) {
+        LineHost lh;
+        build_line(c, l, cb, (int32_t)toff, lh);
+        cb += c->lines[l].n_cells;
+        L.max_nodes = std::max(L.max_nodes, c->lines[l].n_cells + 1);
+        for (int s = 0; s < 4; ++s) L.total_slots += lh.cap[s];
+        toff += (int64_t)lh.table.size();
+        L.n_layer += (int32_t)lh.layer_cell.size();
+        if (lines_out) lines_out->push_back(std::move(lh));
+    }
+    L.n_cells = cb;
+    L.n_nodes = cb + c->n_lines;
+    L.table_floats = toff;
+    return L;
+}
+
+// Carve (or size, when the carver is dry) every device buffer.
+void carve(Carver& cv, const Layout& L, pic1d_state* st) {
+    pic1d_state dummy;
+    pic1d_state* s = st ? st : &dummy;
+    for (int b = 0; b < 2; ++b) {
+        s->cell[b] = cv.take<int32_t>(L.total_slots);
+        s->off[b] = cv.take<float>(L.total_slots);
+        s->u[b] = cv.take<float>(L.total_slots);
+        s->id[b] = cv.take<uint64_t>(L.total_slots);
+    }
+    s->seg_base = cv.take<int64_t>(L.nseg);
+    s->seg_cap = cv.take<int32_t>(L.nseg);
+    s->n_cur = cv.take<int32_t>(L.nseg);
+    s->alloc = cv.take<int32_t>(L.nseg);
+    s->new_count = cv.take<int32_t>(L.nseg);
+    s->tile_prefix = cv.take<int32_t>(L.nseg + 1);
+    s->dlines = cv.take<LineDev>(L.n_lines);
+    s->E = cv.take<double>(L.n_cells);
+    s->J = cv.take<unsigned long long>(L.n_cells);
+    s->j_last = cv.take<double>(L.n_cells);
+    s->E_sum = cv.take<double>(L.n_cells);
+    s->j_sum = cv.take<double>(L.n_cells);
+    s->hist[0] = cv.take<int32_t>(4 * (size_t)L.n_cells);
+    s->hist[1] = cv.take<int32_t>(4 * (size_t)L.n_cells);
+    s->cursor = cv.take<int32_t>(4 * (size_t)L.n_cells);
+    s->pair_step = cv.take<int32_t>(L.n_cells);
+    s->pair_last = cv.take<int32_t>(L.n_cells);
+    s->cell_line = cv.take<int32_t>(L.n_cells);
+    s->pair_sum = cv.take<long long>(L.n_cells);
+    s->n_sum = cv.take<long long>(4 * (size_t)L.n_cells);
+    s->avg_count = cv.take<long long>(1);
+    s->nodes = cv.take<float4>(L.n_nodes);
+    s->rc_nodes = cv.take<double>(L.n_nodes);
+    s->table = cv.take<float>(std::max<int64_t>(L.table_floats, 1));
+    s->layer_cell = cv.take<int32_t>(std::max(L.n_layer, 1));
+    s->layer_line = cv.take<int32_t>(std::max(L.n_layer, 1));
+    s->layer_target = cv.take<int32_t>(std::max(L.n_layer, 1));
+    s->counters = cv.take<unsigned long long>(NCOUNT * (size_t)L.n_lines);
+    s->sc = cv.take<DevScalars>(1);
+    s->rho = cv.take<unsigned long long>(L.max_nodes);
+    s->mom_out = cv.take<double>(8);
+}
+
+PushArgs push_args(pic1d_state* st) {
+    PushArgs a{};
+    const int b = st->cur;
+    a.cell = st->cell[b]; a.off = st->off[b]; a.u = st->u[b]; a.id = st->id[b];
+    a.seg_base = st->seg_base; a.seg_cap = st->seg_cap; a.n_cur = st->n_cur; a.alloc = st->alloc;
+    a.tile_prefix = st->tile_prefix; a.nseg = st->lay.nseg;
+    a.nlg = st->cfg.table_nlg; a.ns = st->cfg.table_ns;
+    a.pairs = st->cfg.pairs; a.conversion = st->cfg.conversion;
+    a.gravity = st->cfg.atmosphere && st->cfg.gravity;
+    a.lines = st->dlines; a.E = st->E; a.J = st->J; a.nodes = st->nodes; a.rc_nodes = st->rc_nodes;
+    a.table = st->table; a.hist[0] = st->hist[0]; a.hist[1] = st->hist[1];
+    a.pair_step = st->pair_step; a.counters = st->counters; a.sc = st->sc;
+    a.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); a.key1 = (uint32_t)(st->cfg.seed >> 32);
+    const double mr = st->cfg.mass_ratio;
+    const double sign[4] = {-1.0, 1.0, -1.0, 1.0};
+    const double mass[4] = {1.0, 1.0, 1.0, mr};
+    for (int s = 0; s < 4; ++s) {
+        a.sign[s] = sign[s];
+        a.qm[s] = (float)(sign[s] / mass[s]);
+        a.inv_mass[s] = (float)(1.0 / mass[s]);
+    }
+    return a;
+}
+
+BookArgs book_args(pic1d_state* st) {
+    BookArgs b{};
+    b.n_cur = st->n_cur; b.alloc = st->alloc; b.seg_cap = st->seg_cap; b.tile_prefix = st->tile_prefix;
+    b.nseg = st->lay.nseg; b.sc = st->sc;
+    return b;
+}
+
+// Event pair around one kernel launch when profiling is on; returns the pair index or -1.
+int prof_begin(pic1d_state* st, int kid) {
+    if (!st->prof_on) return -1;
+    const size_t k = st->ev_kernel.size();
+    while (st->ev_pool.size() < 2 * (k + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        st->ev_pool.push_back(e);
+    }
+    st->ev_kernel.push_back(kid);
+    (void)hipEventRecord(st->ev_pool[2 * k], st->stream);
+    return (int)k;
+}
+
+void prof_end(pic1d_state* st, int k) {
+    if (k >= 0) (void)hipEventRecord(st->ev_pool[2 * k + 1], st->stream);
+}
+
+// After the stream has been synchronised: accumulate the recorded durations.
+void prof_collect(pic1d_state* st) {
+    for (size_t k = 0; k < st->ev_kernel.size(); ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, st->ev_pool[2 * k], st->ev_pool[2 * k + 1]) == hipSuccess) {
+            st->prof_ms[st->ev_kernel[k]] += ms;
+            st->prof_n[st->ev_kernel[k]] += 1;
+        }
+    }
+    st->ev_kernel.clear();
+}
+
+int launch_push(pic1d_state* st) {
+    PushArgs a = push_args(st);
+    const int pk = prof_begin(st, 0);
+    switch (st->backend) {
+        case RICS_OFF: hipLaunchKernelGGL(k_push<RICS_OFF>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
+        case RICS_EXACT: hipLaunchKernelGGL(k_push<RICS_EXACT>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
+        case RICS_TABLE: hipLaunchKernelGGL(k_push<RICS_TABLE>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
+        default: return fail(st, PIC1D_EINVAL, "RICS backend not available in this build");
+    }
+    prof_end(st, pk);
+    return PIC1D_OK;
+}
+
+int launch_plan(pic1d_state* st, int advance) {
+    const int pk = prof_begin(st, 3);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, st->stream, book_args(st), advance);
+    prof_end(st, pk);
+    return PIC1D_OK;
+}
+
+int launch_hist(pic1d_state* st) {
+    // recount H[step & 1] from the live particles
+    HistArgs h{};
+    h.cell = st->cell[st->cur]; h.seg_base = st->seg_base; h.n_cur = st->n_cur; h.tile_prefix = st->tile_prefix;
+    h.nseg = st->lay.nseg; h.lines = st->dlines; h.hist = st->hist[st->host_step & 1];
+    HIP_TRY(st, hipMemsetAsync(h.hist, 0, 4 * sizeof(int32_t) * (size_t)st->lay.n_cells, st->stream));
+    hipLaunchKernelGGL(k_hist, dim3(st->aux_blocks), dim3(PUSH_TPB), 0, st->stream, h);
+    return PIC1D_OK;
+}
+
+int launch_sort(pic1d_state* st) {
+    SortArgs s{};
+    const int b = st->cur, o = 1 - st->cur;
+    s.cell = st->cell[b]; s.off = st->off[b]; s.u = st->u[b]; s.id = st->id[b];
+    s.cell2 = st->cell[o]; s.off2 = st->off[o]; s.u2 = st->u[o]; s.id2 = st->id[o];
+    s.seg_base = st->seg_base; s.seg_cap = st->seg_cap; s.n_cur = st->n_cur; s.alloc = st->alloc;
+    s.tile_prefix = st->tile_prefix;
+    s.nseg = st->lay.nseg; s.lines = st->dlines; s.hist[0] = st->hist[0]; s.hist[1] = st->hist[1];
+    s.cursor = st->cursor; s.new_count = st->new_count; s.sc = st->sc;
+    const int pk = prof_begin(st, 4);
+    hipLaunchKernelGGL(k_sort_scan, dim3(st->lay.nseg), dim3(1024), 0, st->stream, s);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(st->aux_blocks), dim3(PUSH_TPB), 0, st->stream, s);
+    hipLaunchKernelGGL(k_sort_finish, dim3((st->lay.nseg + 255) / 256), dim3(256), 0, st->stream, s);
+    prof_end(st, pk);
+    st->cur = o;
+    return launch_plan(st, 0);
+}
+
+int check_error(pic1d_state* st) {
+    DevScalars h{};
+    HIP_TRY(st, hipMemcpyAsync(&h, st->sc, sizeof(h), hipMemcpyDeviceToHost, st->stream));
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    if (h.err != 0) {
+        st->frozen = h.err;
+        return fail(st, h.err, h.err == PIC1D_ECAPACITY ? "particle capacity exceeded (state frozen)"
+                                                         : "non-finite momentum (state frozen)");
+    }
+    return PIC1D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic1d_workspace_size(const pic1d_config* cfg, size_t* bytes) {
+    const char* why = validate_config(cfg);
+    if (why[0]) return fail(nullptr, PIC1D_EINVAL, why);
+    if (!bytes) return fail(nullptr, PIC1D_EINVAL, "bytes is NULL");
+    const Layout L = plan_layout(cfg, nullptr);
+    Carver cv(nullptr);
+    carve(cv, L, nullptr);
+    *bytes = cv.off + 256;
+    return PIC1D_OK;
+}
+
+int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
+    if (!out) return fail(nullptr, PIC1D_EINVAL, "out is NULL");
+    *out = nullptr;
+    const char* why = validate_config(cfg);
+    if (why[0]) return fail(nullptr, PIC1D_EINVAL, why);
+    if (cfg->rics_backend == PIC1D_RICS_MLP && !cfg->mlp_weights)
+        return fail(nullptr, PIC1D_EINVAL, "MLP backend needs mlp_weights");
+    pic1d_state* st = new pic1d_state();
+    st->cfg = *cfg;
+    st->lines_cfg.assign(cfg->lines, cfg->lines + cfg->n_lines);
+    st->cfg.lines = st->lines_cfg.data();
+    st->stream = (hipStream_t)cfg->stream;
+    st->backend = cfg->rics_backend;
+    st->lay = plan_layout(&st->cfg, &st->lines);
+    Carver dry(nullptr);
+    carve(dry, st->lay, nullptr);
+    if (!cfg->workspace || cfg->workspace_bytes < dry.off + 256 || ((uintptr_t)cfg->workspace & 255)) {
+        delete st;
+        return fail(nullptr, PIC1D_ENOMEM, "workspace missing, misaligned or smaller than pic1d_workspace_size");
+    }
+    Carver cv(cfg->workspace);
+    carve(cv, st->lay, st);
+
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete st;
+        return fail(nullptr, PIC1D_EDEVICE, "no HIP device");
+    }
+    st->n_cu = prop.multiProcessorCount;
+    int occ = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_push<RICS_TABLE>, PUSH_TPB, 0);
+    occ = std::max(1, std::min(occ, 8));
+    st->push_blocks = st->n_cu * occ;
+    st->aux_blocks = st->n_cu * 4;
+
+    const hipStream_t s = st->stream;
+    auto bail = [&](int code, const std::string& m) {
+        g_init_error = m;
+        delete st;
+        return code;
+    };
+#define INIT_TRY(expr)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return bail(PIC1D_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+    INIT_TRY(hipMemsetAsync(cfg->workspace, 0, cv.off, s));
+    // segments
+    const int nseg = st->lay.nseg;
+    st->seg_base_h.assign(nseg, 0);
+    st->seg_cap_h.assign(nseg, 0);
+    int64_t acc = 0;
+    for (int l = 0; l < st->lay.n_lines; ++l)
+        for (int sp = 0; sp < 4; ++sp) {
+            st->seg_base_h[4 * l + sp] = acc;
+            st->seg_cap_h[4 * l + sp] = (int32_t)st->lines[l].cap[sp];
+            acc += st->lines[l].cap[sp];
+        }
+    std::vector<LineDev> ld(st->lay.n_lines);
+    std::vector<float> nodes;
+    std::vector<double> rcn;
+    std::vector<float> table;
+    std::vector<int32_t> lc, ll, lt, cell_line;
+    for (int l = 0; l < st->lay.n_lines; ++l) {
+        const LineHost& lh = st->lines[l];
+        ld[l] = lh.dev;
+        nodes.insert(nodes.end(), lh.nodes.begin(), lh.nodes.end());
+        rcn.insert(rcn.end(), lh.rc.begin(), lh.rc.end());
+        table.insert(table.end(), lh.table.begin(), lh.table.end());
+        for (size_t k = 0; k < lh.layer_cell.size(); ++k) {
+            lc.push_back(lh.dev.cell_base + lh.layer_cell[k]);
+            ll.push_back(l);
+            lt.push_back(lh.layer_target[k]);
+        }
+        cell_line.insert(cell_line.end(), lh.dev.n_cells, l);
+    }
+    INIT_TRY(hipMemcpyAsync(st->seg_base, st->seg_base_h.data(), nseg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(st->seg_cap, st->seg_cap_h.data(), nseg * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(st->dlines, ld.data(), ld.size() * sizeof(LineDev), hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(st->nodes, nodes.data(), nodes.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(st->rc_nodes, rcn.data(), rcn.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (!table.empty())
+        INIT_TRY(hipMemcpyAsync(st->table, table.data(), table.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    if (!lc.empty()) {
+        INIT_TRY(hipMemcpyAsync(st->layer_cell, lc.data(), lc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        INIT_TRY(hipMemcpyAsync(st->layer_line, ll.data(), ll.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        INIT_TRY(hipMemcpyAsync(st->layer_target, lt.data(), lt.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    INIT_TRY(hipMemcpyAsync(st->cell_line, cell_line.data(), cell_line.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+
+    // initial pair plasma
+    std::vector<int32_t> alloc0(nseg, 0);
+    for (int l = 0; l < st->lay.n_lines; ++l) {
+        const pic1d_line& ln = st->lines_cfg[l];
+        const int64_t np = (ln.init_mode == PIC1D_INIT_EMPTY) ? 0 : (int64_t)ln.ppc_init * ln.n_cells;
+        if (np == 0) continue;
+        if (np > st->seg_cap_h[4 * l] || np > st->seg_cap_h[4 * l + 1]) return bail(PIC1D_EINVAL, "capacity below the initial pairs");
+        InitArgs ia{};
+        ia.cell = st->cell[0]; ia.off = st->off[0]; ia.u = st->u[0]; ia.id = st->id[0];
+        ia.base_e = st->seg_base_h[4 * l]; ia.base_p = st->seg_base_h[4 * l + 1];
+        ia.n_pairs = np; ia.ppc = ln.ppc_init; ia.line = l; ia.mode = ln.init_mode;
+        ia.log10_gmax = ln.init_mode == PIC1D_INIT_HOT ? log10(ln.init_gamma_max) : 0.0;
+        const double us = ln.init_beta / sqrt(1.0 - ln.init_beta * ln.init_beta);
+        ia.u_stream = (cfg->j_twist >= 0.0 ? 1.0 : -1.0) * us;
+        ia.id_base = (uint64_t)l << 40;
+        ia.key0 = (uint32_t)(cfg->seed & 0xFFFFFFFFu); ia.key1 = (uint32_t)(cfg->seed >> 32);
+        hipLaunchKernelGGL(k_init_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, ia);
+        alloc0[4 * l] = alloc0[4 * l + 1] = (int32_t)np;
+    }
+    INIT_TRY(hipMemcpyAsync(st->alloc, alloc0.data(), nseg * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (launch_plan(st, 0) != PIC1D_OK) return bail(PIC1D_EDEVICE, st->err);
+    if (launch_hist(st) != PIC1D_OK) return bail(PIC1D_EDEVICE, st->err);
+    INIT_TRY(hipStreamSynchronize(s));
+    INIT_TRY(hipGetLastError());
+#undef INIT_TRY
+    *out = st;
+    return PIC1D_OK;
+}
+
+int pic1d_step(pic1d_state* st, int32_t n_steps) {
+    if (!st || n_steps < 0) return fail(st, PIC1D_EINVAL, "bad arguments");
+    if (st->frozen) return fail(st, PIC1D_ESTATE, "state frozen by an earlier error");
+    const int nt = st->lay.n_cells;
+    FieldArgs f{};
+    for (int32_t i = 0; i < n_steps; ++i) {
+        int rc = launch_push(st);
+        if (rc) return rc;
+        if (st->cfg.atmosphere && st->lay.n_layer > 0) {
+            AtmArgs a{};
+            const int b = st->cur;
+            a.cell = st->cell[b]; a.off = st->off[b]; a.u = st->u[b]; a.id = st->id[b];
+            a.seg_base = st->seg_base; a.seg_cap = st->seg_cap; a.alloc = st->alloc; a.lines = st->dlines;
+            a.hist[0] = st->hist[0]; a.hist[1] = st->hist[1];
+            a.layer_cell = st->layer_cell; a.layer_line = st->layer_line; a.layer_target = st->layer_target;
+            a.n_layer = st->lay.n_layer; a.counters = st->counters; a.sc = st->sc;
+            a.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); a.key1 = (uint32_t)(st->cfg.seed >> 32);
+            a.sig_e = (float)sqrt(st->cfg.atm_T);
+            a.sig_i = (float)sqrt(st->cfg.atm_T / st->cfg.mass_ratio);
+            const int blocks = std::min(st->aux_blocks, (st->lay.n_layer * 64 + 255) / 256);
+            const int pk = prof_begin(st, 1);
+            hipLaunchKernelGGL(k_atmosphere, dim3(std::max(blocks, 1)), dim3(256), 0, st->stream, a);
+            prof_end(st, pk);
+        }
+        f.E = st->E; f.J = st->J; f.j_last = st->j_last; f.hist[0] = st->hist[0]; f.hist[1] = st->hist[1];
+        f.pair_step = st->pair_step; f.pair_last = st->pair_last; f.E_sum = st->E_sum; f.j_sum = st->j_sum;
+        f.pair_sum = st->pair_sum; f.n_sum = st->n_sum; f.avg_count = st->avg_count; f.cell_line = st->cell_line;
+        f.lines = st->dlines; f.n_total = nt; f.frozen = st->cfg.frozen_field; f.avg_start = st->cfg.avg_start_step;
+        f.sc = st->sc;
+        const int pk = prof_begin(st, 2);
+        hipLaunchKernelGGL(k_field, dim3(std::min(st->aux_blocks, (nt + 255) / 256)), dim3(256), 0, st->stream, f);
+        prof_end(st, pk);
+        launch_plan(st, 1);
+        st->host_step += 1;
+        if (st->cfg.sort_interval > 0 && st->host_step % st->cfg.sort_interval == 0) {
+            rc = launch_sort(st);
+            if (rc) return rc;
+        }
+    }
+    HIP_TRY(st, hipGetLastError());
+    const int rc = check_error(st);
+    prof_collect(st);
+    return rc;
+}
+
+int pic1d_profile(pic1d_state* st, int32_t enable) {
+    if (!st) return fail(st, PIC1D_EINVAL, "bad arguments");
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    prof_collect(st);
+    for (int k = 0; k < 8; ++k) { st->prof_ms[k] = 0.0; st->prof_n[k] = 0; }
+    st->prof_on = enable ? 1 : 0;
+    return PIC1D_OK;
+}
+
+int pic1d_profile_read(pic1d_state* st, pic1d_profile_out* out) {
+    if (!st || !out) return fail(st, PIC1D_EINVAL, "bad arguments");
+    for (int k = 0; k < 8; ++k) { out->ms[k] = st->prof_ms[k]; out->launches[k] = st->prof_n[k]; }
+    return PIC1D_OK;
+}
+
+int pic1d_moments(pic1d_state* st, int32_t line, int32_t flags, pic1d_moments_out* out) {
+    if (!st || !out || line < 0 || line >= st->lay.n_lines) return fail(st, PIC1D_EINVAL, "bad arguments");
+    const LineHost& lh = st->lines[line];
+    const int n = lh.dev.n_cells, cb = lh.dev.cell_base;
+    const hipStream_t s = st->stream;
+    HIP_TRY(st, hipMemsetAsync(st->rho, 0, sizeof(unsigned long long) * (n + 1), s));
+    HIP_TRY(st, hipMemsetAsync(st->mom_out, 0, 8 * sizeof(double), s));
+    MomArgs m{};
+    m.cell = st->cell[st->cur]; m.off = st->off[st->cur]; m.u = st->u[st->cur];
+    m.seg_base = st->seg_base; m.n_cur = st->n_cur; m.tile_prefix = st->tile_prefix; m.nseg = st->lay.nseg;
+    m.line = line; m.lines = st->dlines; m.E = st->E; m.rho = st->rho; m.out = st->mom_out;
+    const double sign[4] = {-1.0, 1.0, -1.0, 1.0};
+    for (int k = 0; k < 4; ++k) m.sign[k] = sign[k];
+    m.mass_ratio = st->cfg.mass_ratio;
+    hipLaunchKernelGGL(k_moments_particles, dim3(st->aux_blocks), dim3(PUSH_TPB), 0, s, m);
+    hipLaunchKernelGGL(k_moments_grid, dim3(std::max(1, std::min(256, (n + 256) / 256))), dim3(256), 0, s, m);
+    double mo[8];
+    DevScalars sc{};
+    long long avg = 0;
+    std::vector<int32_t> ncur(4);
+    std::vector<unsigned long long> cnt(NCOUNT);
+    HIP_TRY(st, hipMemcpyAsync(mo, st->mom_out, sizeof(mo), hipMemcpyDeviceToHost, s));
+    HIP_TRY(st, hipMemcpyAsync(&sc, st->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(st, hipMemcpyAsync(&avg, st->avg_count, sizeof(avg), hipMemcpyDeviceToHost, s));
+    HIP_TRY(st, hipMemcpyAsync(ncur.data(), st->n_cur + 4 * line, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(st, hipMemcpyAsync(cnt.data(), st->counters + NCOUNT * line, NCOUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    const bool average = (flags & PIC1D_MOM_AVERAGE) != 0;
+    std::vector<int32_t> hist(4 * (size_t)n);
+    std::vector<long long> nsum, psum;
+    std::vector<int32_t> plast;
+    std::vector<double> E(n), jv(n);
+    if (average) {
+        nsum.resize(4 * (size_t)n);
+        psum.resize(n);
+        HIP_TRY(st, hipMemcpyAsync(nsum.data(), st->n_sum + 4 * (size_t)cb, nsum.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(st, hipMemcpyAsync(psum.data(), st->pair_sum + cb, psum.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(st, hipMemcpyAsync(E.data(), st->E_sum + cb, n * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(st, hipMemcpyAsync(jv.data(), st->j_sum + cb, n * 8, hipMemcpyDeviceToHost, s));
+    } else {
+        plast.resize(n);
+        HIP_TRY(st, hipStreamSynchronize(s));
+        HIP_TRY(st, hipMemcpyAsync(hist.data(), st->hist[sc.step & 1] + 4 * (size_t)cb, hist.size() * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(st, hipMemcpyAsync(plast.data(), st->pair_last + cb, n * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(st, hipMemcpyAsync(E.data(), st->E + cb, n * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(st, hipMemcpyAsync(jv.data(), st->j_last + cb, n * 8, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(st, hipStreamSynchronize(s));
+    const double Q = lh.dev.Q, C = lh.dev.C, ppc0 = st->cfg.ppc0;
+    const double jn = ppc0 * Q * C;   // n0 e c in code units
+    const double na = average ? (double)std::max(avg, 1ll) : 1.0;
+    for (int sp = 0; sp < 4; ++sp)
+        if (out->n_cell[sp])
+            for (int c = 0; c < n; ++c)
+                out->n_cell[sp][c] = (average ? (double)nsum[4 * (size_t)c + sp] : (double)hist[4 * (size_t)c + sp]) / (na * ppc0);
+    if (out->j) for (int c = 0; c < n; ++c) out->j[c] = jv[c] / (na * jn);
+    if (out->E) for (int c = 0; c < n; ++c) out->E[c] = E[c] / na;
+    if (out->pair_rate)
+        for (int c = 0; c < n; ++c) out->pair_rate[c] = average ? (double)psum[c] / na : (double)plast[c];
+    out->gauss_residual = mo[0] / (4.0 * M_PI * Q * ppc0);
+    out->v_circuit = -mo[1] / (C * C);
+    out->energy_kinetic = mo[2];
+    out->energy_field = mo[3] / (8.0 * M_PI);
+    for (int k = 0; k < 4; ++k) out->count[k] = 0;
+    out->step = (int64_t)sc.step;
+    out->avg_steps = avg;
+    for (int k = 0; k < NCOUNT; ++k) out->counters[k] = (int64_t)cnt[k];
+    // live counts: the histogram of the current particles (absorbed ones excluded)
+    {
+        std::vector<int32_t> hc(4 * (size_t)n);
+        HIP_TRY(st, copy_sync(st->stream, hc.data(), st->hist[sc.step & 1] + 4 * (size_t)cb, hc.size() * 4, hipMemcpyDeviceToHost));
+        for (int c = 0; c < n; ++c)
+            for (int k = 0; k < 4; ++k) out->count[k] += hc[4 * (size_t)c + k];
+    }
+    if (flags & PIC1D_MOM_RESET) {
+        HIP_TRY(st, hipMemsetAsync(st->n_sum, 0, 4 * 8 * (size_t)st->lay.n_cells, s));
+        HIP_TRY(st, hipMemsetAsync(st->pair_sum, 0, 8 * (size_t)st->lay.n_cells, s));
+        HIP_TRY(st, hipMemsetAsync(st->E_sum, 0, 8 * (size_t)st->lay.n_cells, s));
+        HIP_TRY(st, hipMemsetAsync(st->j_sum, 0, 8 * (size_t)st->lay.n_cells, s));
+        HIP_TRY(st, hipMemsetAsync(st->avg_count, 0, 8, s));
+        HIP_TRY(st, hipStreamSynchronize(s));
+    }
+    (void)ncur;
+    return PIC1D_OK;
+}
+
+void pic1d_free(pic1d_state* st) { delete st; }
+
+const char* pic1d_last_error(const pic1d_state* st) { return st ? st->err.c_str() : g_init_error.c_str(); }
+
+int pic1d_get_particles(pic1d_state* st, int32_t line, int32_t species, int64_t capacity, int64_t* count,
+                        int32_t* cell, float* offset, float* u, uint64_t* id) {
+    if (!st || !count || line < 0 || line >= st->lay.n_lines || species < 0 || species > 3)
+        return fail(st, PIC1D_EINVAL, "bad arguments");
+    const int seg = 4 * line + species;
+    int32_t n = 0;
+    HIP_TRY(st, hipMemcpyAsync(&n, st->n_cur + seg, 4, hipMemcpyDeviceToHost, st->stream));
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    const int64_t b = st->seg_base_h[seg];
+    std::vector<int32_t> c(n);
+    std::vector<float> o(n), uu(n);
+    std::vector<uint64_t> ii(n);
+    const int k = st->cur;
+    if (n > 0) {
+        HIP_TRY(st, copy_sync(st->stream, c.data(), st->cell[k] + b, 4 * (size_t)n, hipMemcpyDeviceToHost));
+        HIP_TRY(st, copy_sync(st->stream, o.data(), st->off[k] + b, 4 * (size_t)n, hipMemcpyDeviceToHost));
+        HIP_TRY(st, copy_sync(st->stream, uu.data(), st->u[k] + b, 4 * (size_t)n, hipMemcpyDeviceToHost));
+        HIP_TRY(st, copy_sync(st->stream, ii.data(), st->id[k] + b, 8 * (size_t)n, hipMemcpyDeviceToHost));
+    }
+    int64_t live = 0;
+    for (int32_t i = 0; i < n; ++i) live += (c[i] != DEAD_CELL);
+    *count = live;
+    if (live > capacity) return fail(st, PIC1D_EINVAL, "capacity of the output arrays too small");
+    int64_t w = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (c[i] == DEAD_CELL) continue;
+        if (cell) cell[w] = c[i];
+        if (offset) offset[w] = o[i];
+        if (u) u[w] = uu[i];
+        if (id) id[w] = ii[i];
+        ++w;
+    }
+    return PIC1D_OK;
+}
+
+int pic1d_set_particles(pic1d_state* st, int32_t line, int32_t species, int64_t count, const int32_t* cell,
+                        const float* offset, const float* u, const uint64_t* id) {
+    if (!st || line < 0 || line >= st->lay.n_lines || species < 0 || species > 3 || count < 0)
+        return fail(st, PIC1D_EINVAL, "bad arguments");
+    if (count > 0 && (!cell || !offset || !u || !id)) return fail(st, PIC1D_EINVAL, "NULL particle array");
+    const int seg = 4 * line + species;
+    if (count > st->seg_cap_h[seg]) return fail(st, PIC1D_ECAPACITY, "more particles than the species capacity");
+    const int n = st->lines[line].dev.n_cells;
+    for (int64_t i = 0; i < count; ++i)
+        if (cell[i] < 0 || cell[i] >= n || !(offset[i] >= 0.0f && offset[i] < 1.0f) || !isfinite(u[i]))
+            return fail(st, PIC1D_EINVAL, "particle outside the line or non-finite");
+    const int64_t b = st->seg_base_h[seg];
+    const int k = st->cur;
+    if (count > 0) {
+        HIP_TRY(st, copy_sync(st->stream, st->cell[k] + b, cell, 4 * (size_t)count, hipMemcpyHostToDevice));
+        HIP_TRY(st, copy_sync(st->stream, st->off[k] + b, offset, 4 * (size_t)count, hipMemcpyHostToDevice));
+        HIP_TRY(st, copy_sync(st->stream, st->u[k] + b, u, 4 * (size_t)count, hipMemcpyHostToDevice));
+        HIP_TRY(st, copy_sync(st->stream, st->id[k] + b, id, 8 * (size_t)count, hipMemcpyHostToDevice));
+    }
+    const int32_t c32 = (int32_t)count;
+    HIP_TRY(st, copy_sync(st->stream, st->alloc + seg, &c32, 4, hipMemcpyHostToDevice));
+    launch_plan(st, 0);
+    int rc = launch_hist(st);
+    if (rc) return rc;
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    return PIC1D_OK;
+}
+
+int pic1d_get_field(pic1d_state* st, int32_t line, double* E) {
+    if (!st || !E || line < 0 || line >= st->lay.n_lines) return fail(st, PIC1D_EINVAL, "bad arguments");
+    const LineDev& d = st->lines[line].dev;
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    HIP_TRY(st, copy_sync(st->stream, E, st->E + d.cell_base, 8 * (size_t)d.n_cells, hipMemcpyDeviceToHost));
+    return PIC1D_OK;
+}
+
+int pic1d_set_field(pic1d_state* st, int32_t line, const double* E) {
+    if (!st || !E || line < 0 || line >= st->lay.n_lines) return fail(st, PIC1D_EINVAL, "bad arguments");
+    const LineDev& d = st->lines[line].dev;
+    for (int i = 0; i < d.n_cells; ++i)
+        if (!isfinite(E[i])) return fail(st, PIC1D_EINVAL, "non-finite field value");
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    HIP_TRY(st, copy_sync(st->stream, st->E + d.cell_base, E, 8 * (size_t)d.n_cells, hipMemcpyHostToDevice));
+    return PIC1D_OK;
+}
+
+int pic1d_set_step(pic1d_state* st, int64_t step) {
+    if (!st || step < 0) return fail(st, PIC1D_EINVAL, "bad arguments");
+    // the per-cell counts live in H[step & 1]; move them along with the counter
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    DevScalars sc{};
+    HIP_TRY(st, copy_sync(st->stream, &sc, st->sc, sizeof(sc), hipMemcpyDeviceToHost));
+    const int from = (int)(sc.step & 1), to = (int)(step & 1);
+    if (from != to) {
+        const size_t bytes = 4 * sizeof(int32_t) * (size_t)st->lay.n_cells;
+        HIP_TRY(st, copy_sync(st->stream, st->hist[to], st->hist[from], bytes, hipMemcpyDeviceToDevice));
+        HIP_TRY(st, hipMemsetAsync(st->hist[from], 0, bytes, st->stream));
+    }
+    sc.step = (uint64_t)step;
+    HIP_TRY(st, copy_sync(st->stream, st->sc, &sc, sizeof(sc), hipMemcpyHostToDevice));
+    st->host_step = (uint64_t)step;
+    return PIC1D_OK;
+}
+
+int pic1d_rics_eval(pic1d_state* st, int32_t line, int64_t n, const float* s_cells, const float* u, float* F,
+                    float* ndot, float* eps) {
+    if (!st || line < 0 || line >= st->lay.n_lines || n < 0 || (n > 0 && (!s_cells || !u || !F || !ndot || !eps)))
+        return fail(st, PIC1D_EINVAL, "bad arguments");
+    if (n == 0) return PIC1D_OK;
+    PushArgs a = push_args(st);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    switch (st->backend) {
+        case RICS_OFF: hipLaunchKernelGGL(k_rics_eval<RICS_OFF>, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
+        case RICS_EXACT: hipLaunchKernelGGL(k_rics_eval<RICS_EXACT>, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
+        case RICS_TABLE: hipLaunchKernelGGL(k_rics_eval<RICS_TABLE>, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
+        default: return fail(st, PIC1D_EINVAL, "RICS backend not available in this build");
+    }
+    HIP_TRY(st, hipGetLastError());
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    return PIC1D_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,280 @@
+"""Python binding of libpic1d.so (argument marshalling only).
+
+Every step of the PIC path runs in the HIP kernels of the library; this module
+builds the C config struct, allocates the device workspace as a torch uint8
+tensor, passes torch's current HIP stream, and copies results in and out.  It
+raises if the library has not been built: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .config import RICS, CONVERSION, INIT, SPECIES, complete_config
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpic1d.so")
+_lib = None
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ECAPACITY", -4: "EDEVICE", -5: "ENONFINITE",
+          -6: "ESTATE"}
+
+
+class Pic1dError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pic1d {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CLine(ctypes.Structure):
+    _fields_ = [("r_eq", ctypes.c_double), ("n_cells", ctypes.c_int32), ("ppc_init", ctypes.c_int32),
+                ("init_mode", ctypes.c_int32), ("pad0", ctypes.c_int32), ("init_gamma_max", ctypes.c_double),
+                ("init_beta", ctypes.c_double), ("capacity", ctypes.c_int64 * 4)]
+
+
+class CConfig(ctypes.Structure):
+    _fields_ = [("n_lines", ctypes.c_int32), ("pad0", ctypes.c_int32), ("lines", ctypes.POINTER(CLine)),
+                ("b_pole", ctypes.c_double), ("cfl", ctypes.c_double), ("d0_cells", ctypes.c_double),
+                ("ppc0", ctypes.c_double), ("j_twist", ctypes.c_double), ("kT_keV", ctypes.c_double),
+                ("eta_min", ctypes.c_double), ("b_thr", ctypes.c_double), ("mass_ratio", ctypes.c_double),
+                ("rics_backend", ctypes.c_int32), ("table_nlg", ctypes.c_int32), ("table_ns", ctypes.c_int32),
+                ("pairs", ctypes.c_int32), ("conversion", ctypes.c_int32), ("atmosphere", ctypes.c_int32),
+                ("gravity", ctypes.c_int32), ("frozen_field", ctypes.c_int32),
+                ("nmax_over_n0", ctypes.c_double), ("atm_a0", ctypes.c_double), ("atm_h_cells", ctypes.c_double),
+                ("atm_T", ctypes.c_double), ("atm_cut", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("sort_interval", ctypes.c_int32), ("avg_start_step", ctypes.c_int32),
+                ("mlp_weights", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+
+
+class CMoments(ctypes.Structure):
+    _fields_ = [("n_cell", ctypes.POINTER(ctypes.c_double) * 4), ("j", ctypes.POINTER(ctypes.c_double)),
+                ("E", ctypes.POINTER(ctypes.c_double)), ("pair_rate", ctypes.POINTER(ctypes.c_double)),
+                ("gauss_residual", ctypes.c_double), ("v_circuit", ctypes.c_double),
+                ("energy_kinetic", ctypes.c_double), ("energy_field", ctypes.c_double),
+                ("count", ctypes.c_int64 * 4), ("counters", ctypes.c_int64 * 16), ("step", ctypes.c_int64),
+                ("avg_steps", ctypes.c_int64)]
+
+
+COUNTER_NAMES = ("events", "pairs_created", "photons_escaped", "absorbed", "psc_clipped", "limited",
+                 "newton", "atm_injected", "pushed", "draws")
+
+
+class CProfile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
+
+
+KERNELS = ("push", "atmosphere", "field", "plan", "sort")
+
+P = ctypes.c_void_p
+_SIGS = {
+    "pic1d_workspace_size": (ctypes.c_int, [ctypes.POINTER(CConfig), ctypes.POINTER(ctypes.c_size_t)]),
+    "pic1d_init": (ctypes.c_int, [ctypes.POINTER(CConfig), ctypes.POINTER(P)]),
+    "pic1d_step": (ctypes.c_int, [P, ctypes.c_int32]),
+    "pic1d_moments": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(CMoments)]),
+    "pic1d_free": (None, [P]),
+    "pic1d_last_error": (ctypes.c_char_p, [P]),
+    "pic1d_get_particles": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64), P, P, P, P]),
+    "pic1d_set_particles": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P, P, P, P]),
+    "pic1d_get_field": (ctypes.c_int, [P, ctypes.c_int32, P]),
+    "pic1d_set_field": (ctypes.c_int, [P, ctypes.c_int32, P]),
+    "pic1d_set_step": (ctypes.c_int, [P, ctypes.c_int64]),
+    "pic1d_rics_eval": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int64, P, P, P, P, P]),
+    "pic1d_profile": (ctypes.c_int, [P, ctypes.c_int32]),
+    "pic1d_profile_read": (ctypes.c_int, [P, ctypes.POINTER(CProfile)]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+def load():
+    """Load libpic1d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_2609_17661_amd.build.build()")
+        lib = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def make_cconfig(cfg):
+    """C config struct (and the line array it points to) from a complete config dict."""
+    lines = cfg["lines"]
+    arr = (CLine * len(lines))()
+    for i, ln in enumerate(lines):
+        arr[i].r_eq = float(ln["r_eq"])
+        arr[i].n_cells = int(ln["n_cells"])
+        arr[i].ppc_init = int(ln.get("ppc_init", 0))
+        arr[i].init_mode = INIT[ln.get("init", "cold")]
+        arr[i].init_gamma_max = float(ln.get("init_gamma_max", 1.0e4))
+        arr[i].init_beta = float(ln.get("init_beta", 0.0))
+        cap = ln.get("capacity", [0, 0, 0, 0])
+        for s in range(4):
+            arr[i].capacity[s] = int(cap[s])
+    c = CConfig()
+    c.n_lines = len(lines)
+    c.lines = arr
+    for k in ("b_pole", "cfl", "d0_cells", "ppc0", "j_twist", "kT_keV", "eta_min", "b_thr", "mass_ratio",
+              "nmax_over_n0", "atm_a0", "atm_h_cells", "atm_T", "atm_cut"):
+        setattr(c, k, float(cfg[k]))
+    c.rics_backend = RICS[cfg["rics"]]
+    c.table_nlg = int(cfg["table_nlg"])
+    c.table_ns = int(cfg["table_ns"])
+    c.pairs = int(bool(cfg["pairs"]))
+    c.conversion = CONVERSION[cfg["conversion"]]
+    c.atmosphere = int(bool(cfg["atmosphere"]))
+    c.gravity = int(bool(cfg["gravity"]))
+    c.frozen_field = int(bool(cfg["frozen_field"]))
+    c.seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
+    c.sort_interval = int(cfg["sort_interval"])
+    c.avg_start_step = int(cfg["avg_start_step"])
+    return c, arr
+
+
+def workspace_size(cfg):
+    lib = load()
+    c, keep = make_cconfig(complete_config(cfg))
+    n = ctypes.c_size_t(0)
+    rc = lib.pic1d_workspace_size(ctypes.byref(c), ctypes.byref(n))
+    if rc != 0:
+        raise Pic1dError(rc, lib.pic1d_last_error(None).decode())
+    return n.value
+
+
+class Pic1D:
+    """One simulation state on the current HIP device (all lines of a config)."""
+
+    def __init__(self, cfg, device="cuda", mlp_weights=None):
+        import torch
+
+        self._torch = torch
+        self.lib = load()
+        self.cfg = complete_config(cfg)
+        c, self._lines_keep = make_cconfig(self.cfg)
+        n = ctypes.c_size_t(0)
+        rc = self.lib.pic1d_workspace_size(ctypes.byref(c), ctypes.byref(n))
+        if rc != 0:
+            raise Pic1dError(rc, self.lib.pic1d_last_error(None).decode())
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        c.workspace = ctypes.c_void_p(self.workspace.data_ptr())
+        c.workspace_bytes = n.value
+        c.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        if mlp_weights is not None:
+            self._mlp = np.ascontiguousarray(mlp_weights, dtype=np.float32)
+            c.mlp_weights = ctypes.c_void_p(self._mlp.ctypes.data)
+        h = ctypes.c_void_p()
+        rc = self.lib.pic1d_init(ctypes.byref(c), ctypes.byref(h))
+        if rc != 0:
+            raise Pic1dError(rc, self.lib.pic1d_last_error(None).decode())
+        self.h = h
+        self.n_lines = len(self.cfg["lines"])
+
+    def _check(self, rc):
+        if rc != 0:
+            raise Pic1dError(rc, self.lib.pic1d_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pic1d_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        self._check(self.lib.pic1d_step(self.h, int(n)))
+
+    def n_cells(self, line=0):
+        return int(self.cfg["lines"][line]["n_cells"])
+
+    def moments(self, line=0, average=False, reset=False):
+        n = self.n_cells(line)
+        out = CMoments()
+        arrs = {f"n{s}": np.zeros(n) for s in range(4)}
+        arrs.update(j=np.zeros(n), E=np.zeros(n), pair_rate=np.zeros(n))
+        for s in range(4):
+            out.n_cell[s] = arrs[f"n{s}"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        out.j = arrs["j"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        out.E = arrs["E"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        out.pair_rate = arrs["pair_rate"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        flags = (1 if average else 0) | (2 if reset else 0)
+        self._check(self.lib.pic1d_moments(self.h, int(line), flags, ctypes.byref(out)))
+        res = dict(n=np.stack([arrs[f"n{s}"] for s in range(4)]), j=arrs["j"], E=arrs["E"],
+                   pair_rate=arrs["pair_rate"], gauss_residual=out.gauss_residual, v_circuit=out.v_circuit,
+                   energy_kinetic=out.energy_kinetic, energy_field=out.energy_field,
+                   count=[int(x) for x in out.count], step=int(out.step), avg_steps=int(out.avg_steps))
+        res["counters"] = {k: int(out.counters[i]) for i, k in enumerate(COUNTER_NAMES)}
+        return res
+
+    def get_particles(self, line=0, species=0):
+        cnt = ctypes.c_int64(0)
+        # a zero-capacity call reports the live count (and fails with EINVAL if it is non-zero)
+        self.lib.pic1d_get_particles(self.h, line, species, 0, ctypes.byref(cnt), None, None, None, None)
+        n = cnt.value
+        cell = np.zeros(n, dtype=np.int32)
+        off = np.zeros(n, dtype=np.float32)
+        u = np.zeros(n, dtype=np.float32)
+        pid = np.zeros(n, dtype=np.uint64)
+        self._check(self.lib.pic1d_get_particles(self.h, line, species, n, ctypes.byref(cnt), _ptr(cell), _ptr(off),
+                                                 _ptr(u), _ptr(pid)))
+        return dict(cell=cell, off=off, u=u, id=pid)
+
+    def set_particles(self, line, species, cell, off, u, pid):
+        cell = np.ascontiguousarray(cell, dtype=np.int32)
+        off = np.ascontiguousarray(off, dtype=np.float32)
+        u = np.ascontiguousarray(u, dtype=np.float32)
+        pid = np.ascontiguousarray(pid, dtype=np.uint64)
+        self._check(self.lib.pic1d_set_particles(self.h, line, species, cell.size, _ptr(cell), _ptr(off), _ptr(u),
+                                                 _ptr(pid)))
+
+    def get_field(self, line=0):
+        E = np.zeros(self.n_cells(line))
+        self._check(self.lib.pic1d_get_field(self.h, line, _ptr(E)))
+        return E
+
+    def set_field(self, line, E):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        assert E.size == self.n_cells(line)
+        self._check(self.lib.pic1d_set_field(self.h, line, _ptr(E)))
+
+    def profile(self, enable=True):
+        self._check(self.lib.pic1d_profile(self.h, int(bool(enable))))
+
+    def profile_read(self):
+        out = CProfile()
+        self._check(self.lib.pic1d_profile_read(self.h, ctypes.byref(out)))
+        return {k: dict(ms=out.ms[i], launches=int(out.launches[i])) for i, k in enumerate(KERNELS)}
+
+    def set_step(self, step):
+        self._check(self.lib.pic1d_set_step(self.h, int(step)))
+
+    def rics_eval(self, line, s_cells, u):
+        """F_hat, Ndot_hat, eps of the configured backend at device tensors s_cells, u (float32)."""
+        torch = self._torch
+        s_cells = s_cells.to(device=self.workspace.device, dtype=torch.float32).contiguous()
+        u = u.to(device=self.workspace.device, dtype=torch.float32).contiguous()
+        n = s_cells.numel()
+        F = torch.empty_like(s_cells)
+        N = torch.empty_like(s_cells)
+        eps = torch.empty_like(s_cells)
+        self._check(self.lib.pic1d_rics_eval(self.h, int(line), n, ctypes.c_void_p(s_cells.data_ptr()),
+                                             ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(F.data_ptr()),
+                                             ctypes.c_void_p(N.data_ptr()), ctypes.c_void_p(eps.data_ptr())))
+        return F, N, eps

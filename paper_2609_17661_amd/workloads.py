@@ -1,0 +1,43 @@
+"""Synthetic workloads (plain parameter dictionaries; no arithmetic of the method).
+
+Each workload is a config dict accepted by the library binding; tests also hand
+the same dict to the oracle.  The shapes follow the paper's setup (Sec. 3 and
+Appendix B: one dipole line, CFL 0.5, 48 cells per skin depth, B*/B_QED = 10)
+at the sizes of the benchmark configurations:
+
+* CFG1      one line, R_max = 4, 512 cells, 64 e-/e+ per cell each (65,536),
+            cold start, TABLE 256 x 512 at kT = 0.5 keV, pairs off, 1000 steps.
+* CFG1_HOT  CFG1 with gamma log-uniform in [1, 1e4] and pairs on (exercises
+            the drag branches, the stochastic events and pair injection).
+* CFG2      one line, R_max = 30, 65,536 cells, 200 e-/e+ per cell each,
+            surface atmosphere with ions at m_i/m_e = 100, pairs on with
+            curvature conversion, capacity for 1e8 particles, 20,000 steps.
+"""
+
+CFG1 = dict(
+    rics="table", table_nlg=256, table_ns=512, kT_keV=0.5, j_twist=0.5, ppc0=64.0, pairs=False,
+    atmosphere=False, seed=0,
+    lines=[dict(r_eq=4.0, n_cells=512, ppc_init=64, init="cold")],
+)
+CFG1_STEPS = 1000
+
+CFG1_HOT = dict(CFG1, pairs=True, conversion="immediate",
+                lines=[dict(r_eq=4.0, n_cells=512, ppc_init=64, init="hot", init_gamma_max=1.0e4,
+                            capacity=[400000, 400000, 0, 0])])
+
+CFG2 = dict(
+    rics="table", table_nlg=256, table_ns=512, kT_keV=0.5, j_twist=0.5, ppc0=200.0, pairs=True,
+    conversion="curvature", atmosphere=True, mass_ratio=100.0, seed=0, sort_interval=50,
+    lines=[dict(r_eq=30.0, n_cells=65536, ppc_init=200, init="cold",
+                capacity=[46_000_000, 46_000_000, 4_000_000, 4_000_000])],
+)
+CFG2_STEPS = 20000
+
+
+def small(r_eq=4.0, n_cells=96, ppc=16, init="hot", **kw):
+    """A small line for per-step parity tests (the oracle steps it in well under a second)."""
+    line = dict(r_eq=r_eq, n_cells=n_cells, ppc_init=ppc, init=init, init_gamma_max=kw.pop("gamma_max", 1.0e3),
+                capacity=kw.pop("capacity", [400_000, 400_000, 200_000, 200_000]))
+    cfg = dict(rics="exact", kT_keV=0.5, j_twist=0.5, ppc0=float(ppc), seed=kw.pop("seed", 7), lines=[line])
+    cfg.update(kw)
+    return cfg

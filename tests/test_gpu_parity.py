@@ -1,0 +1,260 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import philox, pic
+from paper_2609_17661_amd import Pic1D, Pic1dError, workloads
+
+from . import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(cfg):
+    return Pic1D(cfg)
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# initial state
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("init", ["cold", "hot", "stream"])
+def test_initial_plasma_matches_oracle(init):
+    cfg = workloads.small(n_cells=80, ppc=12, init=init, rics="off")
+    cfg["lines"][0]["init_beta"] = 0.3
+    _print("init", init)
+    sim = _sim(cfg)
+    st = pic.init_state(parity.oracle_config(cfg))
+    for s in (0, 1):
+        G = sim.get_particles(0, s)
+        O = st.parts[0][s]
+        og = np.argsort(G["id"])
+        oo = np.argsort(O["id"])
+        np.testing.assert_array_equal(G["id"][og], O["id"][oo])
+        cell_o = np.floor(O["x"][oo]).astype(np.int32)
+        np.testing.assert_array_equal(G["cell"][og], cell_o)
+        # offsets are 24-bit Philox uniforms: bit-exact
+        np.testing.assert_array_equal(G["off"][og].astype(np.float64), O["x"][oo] - cell_o)
+        np.testing.assert_allclose(G["u"][og], O["u"][oo], rtol=2 ** -23, atol=0)
+    m = sim.moments(0)
+    assert m["count"][:2] == [80 * 12, 80 * 12]
+    assert m["gauss_residual"] < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# per-step parity
+# ---------------------------------------------------------------------------
+CASES = {
+    "exact-hot-immediate": workloads.small(rics="exact", pairs=True, conversion="immediate"),
+    "table-hot-curvature": workloads.small(rics="table", table_nlg=64, table_ns=96, pairs=True,
+                                           conversion="curvature"),
+    "exact-cold-atmosphere": workloads.small(n_cells=160, ppc=8, init="cold", rics="exact", atmosphere=True,
+                                             pairs=True, conversion="curvature"),
+    "off-stream-walls": workloads.small(n_cells=64, ppc=16, init="stream", rics="off"),
+    "exact-two-lines": dict(workloads.small(rics="exact", pairs=True),
+                            lines=[dict(r_eq=4.0, n_cells=96, ppc_init=8, init="hot", init_gamma_max=3e3,
+                                        capacity=[300_000, 300_000, 1000, 1000]),
+                                   dict(r_eq=12.0, n_cells=130, ppc_init=6, init="hot", init_gamma_max=1e3,
+                                        capacity=[300_000, 300_000, 1000, 1000])]),
+    "exact-r30-sorted": workloads.small(r_eq=30.0, n_cells=300, ppc=8, rics="exact", pairs=True,
+                                        conversion="curvature", atmosphere=True, sort_interval=2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_step_parity(name):
+    cfg = CASES[name]
+    if name == "off-stream-walls":
+        cfg["lines"][0]["init_beta"] = 0.4
+    ocfg = parity.oracle_config(cfg)
+    sim = _sim(cfg)
+    _print("parity case", name)
+    total = dict(compared=0, excused=0, new=0)
+    for k in range(4):
+        before = parity.snapshot(sim)
+        sim.step(1)
+        after = parity.snapshot(sim)
+        rep, _ = parity.compare_step(ocfg, before, after)
+        _print(f"  step {k}: {rep}")
+        for key in total:
+            total[key] += rep[key]
+        sim.step(1)   # let the state evolve between compared steps
+    assert total["compared"] > 0
+    assert total["excused"] <= max(3, 1e-3 * total["compared"])
+
+
+def test_cfg1_full_size_parity_and_gauss():
+    """65,536 particles of the R_max = 4 line: compared steps at the start and after 200 steps."""
+    cfg = dict(workloads.CFG1)
+    ocfg = parity.oracle_config(cfg)
+    sim = _sim(cfg)
+    for k in range(2):
+        before = parity.snapshot(sim)
+        sim.step(1)
+        after = parity.snapshot(sim)
+        rep, _ = parity.compare_step(ocfg, before, after)
+        _print("cfg1 step", rep)
+        assert rep["compared"] > 60000   # walls absorb a few thousand over 200 steps
+        sim.step(200)
+    m = sim.moments(0)
+    assert m["gauss_residual"] <= 1e-6
+
+
+def test_cfg1_hot_full_size_parity():
+    cfg = dict(workloads.CFG1_HOT)
+    ocfg = parity.oracle_config(cfg)
+    sim = _sim(cfg)
+    before = parity.snapshot(sim)
+    sim.step(1)
+    after = parity.snapshot(sim)
+    rep, st = parity.compare_step(ocfg, before, after)
+    _print("cfg1-hot step", rep, st.counters[0])
+    assert st.counters[0]["events"] > 1000 and st.counters[0]["pairs_created"] > 100
+    m = sim.moments(0)
+    assert m["counters"]["pairs_created"] == pytest.approx(st.counters[0]["pairs_created"], abs=3)
+    assert m["gauss_residual"] <= 1e-6
+
+
+def test_cascade_gauss_and_counts_over_many_steps():
+    cfg = workloads.small(n_cells=128, ppc=8, rics="exact", pairs=True, atmosphere=True,
+                          conversion="curvature", sort_interval=3)
+    sim = _sim(cfg)
+    sim.step(40)
+    m = sim.moments(0)
+    _print("cascade", m["count"], m["counters"], m["gauss_residual"])
+    assert m["counters"]["pairs_created"] > 0 and m["counters"]["atm_injected"] > 0
+    assert m["gauss_residual"] <= 1e-6
+    # live counts equal the particles the state hands back
+    for s in range(4):
+        assert len(sim.get_particles(0, s)["id"]) == m["count"][s]
+
+
+# ---------------------------------------------------------------------------
+# determinism, sort invariance, errors
+# ---------------------------------------------------------------------------
+def _final(cfg, steps):
+    sim = _sim(cfg)
+    sim.step(steps)
+    out = {}
+    for s in range(4):
+        P = sim.get_particles(0, s)
+        o = np.argsort(P["id"])
+        out[s] = {k: v[o] for k, v in P.items()}
+    return out, sim.get_field(0)
+
+
+def test_result_independent_of_sorting_and_bitwise_reproducible():
+    base = workloads.small(n_cells=128, ppc=8, rics="exact", pairs=True, atmosphere=True)
+    a, Ea = _final(dict(base, sort_interval=0), 25)
+    b, Eb = _final(dict(base, sort_interval=1), 25)
+    c, Ec = _final(dict(base, sort_interval=7), 25)
+    for s in range(4):
+        for k in ("id", "cell", "off", "u"):
+            np.testing.assert_array_equal(a[s][k], b[s][k])
+            np.testing.assert_array_equal(a[s][k], c[s][k])
+    np.testing.assert_array_equal(Ea, Eb)
+    np.testing.assert_array_equal(Ea, Ec)
+
+
+def test_capacity_overflow_freezes_state():
+    cfg = workloads.small(n_cells=64, ppc=8, rics="exact", pairs=True)
+    cfg["lines"][0]["capacity"] = [64 * 8 + 5, 64 * 8 + 5, 64, 64]
+    sim = _sim(cfg)
+    with pytest.raises(Pic1dError) as ei:
+        sim.step(5)
+    assert ei.value.code == -3
+    with pytest.raises(Pic1dError) as ei:
+        sim.step(1)
+    assert ei.value.code == -6
+    sim.moments(0)   # still readable
+
+
+def test_set_particles_and_field_roundtrip():
+    cfg = workloads.small(n_cells=32, ppc=2, rics="off")
+    sim = _sim(cfg)
+    rng = np.random.default_rng(5)
+    n = 50
+    cell = rng.integers(0, 32, n).astype(np.int32)
+    off = rng.random(n).astype(np.float32)
+    u = rng.normal(size=n).astype(np.float32)
+    pid = np.arange(n, dtype=np.uint64) + 1000
+    sim.set_particles(0, 3, cell, off, u, pid)
+    P = sim.get_particles(0, 3)
+    o = np.argsort(P["id"])
+    np.testing.assert_array_equal(P["cell"][o], cell)
+    np.testing.assert_array_equal(P["off"][o], off)
+    np.testing.assert_array_equal(P["u"][o], u)
+    E = rng.normal(size=32)
+    sim.set_field(0, E)
+    np.testing.assert_array_equal(sim.get_field(0), E)
+    with pytest.raises(Pic1dError):
+        sim.set_particles(0, 3, np.array([40], dtype=np.int32), np.array([0.5], dtype=np.float32),
+                          np.array([0.0], dtype=np.float32), np.array([1], dtype=np.uint64))
+
+
+def test_hyperbolic_motion_on_gpu():
+    # positron in a uniform frozen field: u after n kicks exact, x matches the oracle's leapfrog
+    cfg = workloads.small(n_cells=3000, ppc=1, init="empty", rics="off", frozen_field=True, j_twist=0.0)
+    sim = _sim(cfg)
+    a = 1e-3
+    sim.set_field(0, np.full(3000, a))
+    sim.set_particles(0, 1, np.array([10], dtype=np.int32), np.array([0.0], dtype=np.float32),
+                      np.array([0.0], dtype=np.float32), np.array([7], dtype=np.uint64))
+    sim.step(1000)
+    P = sim.get_particles(0, 1)
+    C = 0.5
+    assert P["u"][0] == pytest.approx(1000 * a / C, rel=1e-5)
+    gam = lambda t: math.sqrt(1.0 + (a * (t + 0.5) / C) ** 2)
+    x_exact = 10.0 + C * C / a * (gam(1000) - gam(0))
+    x = P["cell"][0] + float(P["off"][0])
+    assert x == pytest.approx(x_exact, rel=2e-3)
+
+
+# ---------------------------------------------------------------------------
+# RICS functions as the pusher evaluates them
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("backend", ["exact", "table"])
+def test_rics_eval_matches_oracle(backend):
+    import torch
+
+    cfg = workloads.small(r_eq=10.0, n_cells=400, ppc=1, init="empty", rics=backend, table_nlg=256, table_ns=512)
+    sim = _sim(cfg)
+    ocfg = parity.oracle_config(cfg)
+    st = pic.State(ocfg)
+    ln = st.lines[0]
+    rng = np.random.default_rng(11)
+    n = 20000
+    s = rng.uniform(0, 400, n).astype(np.float32)
+    lg = rng.uniform(0, 6, n)
+    sg = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    u = (sg * np.sqrt(np.maximum(10 ** (2 * lg) - 1, 0))).astype(np.float32)
+    F, N, eps = (t.cpu().numpy().astype(np.float64) for t in sim.rics_eval(0, torch.from_numpy(s), torch.from_numpy(u)))
+    xs = s.astype(np.float64)
+    uu = u.astype(np.float64)
+    b, mu, xr, rc = ln.geometry_at(xs)
+    force, _, rate = ln.rics_funcs(xs, b, mu, xr)
+    Fo, No = force(uu), rate(uu)
+    eo = pic.rics.photon_energy(uu, b)
+    # significant where the drag changes u by at least 1e-9 |u| per step
+    sig = np.abs(Fo) * ln.h >= 1e-9 * np.maximum(np.abs(uu), 1e-3)
+    # F ~ (gamma mu - u): near the attractor beta = mu the difference cancels, and float32
+    # inputs carry their rounding into F amplified by (gamma |mu| + |u|) / |gamma mu - u|
+    gam = np.sqrt(1 + uu * uu)
+    cond = (gam * np.abs(mu) + np.abs(uu)) / np.maximum(np.abs(gam * mu - uu), 1e-300)
+    relF_c = (np.abs(F - Fo) / np.abs(Fo) / (1.0 + 1e-2 * cond))[sig]
+    relF = np.abs(F - Fo)[sig] / np.abs(Fo)[sig]
+    sigN = No * ln.h > 1e-9
+    relN = np.abs(N - No)[sigN] / No[sigN]
+    _print(backend, "F rel err median/99%/max", np.median(relF), np.quantile(relF, 0.99), relF.max(),
+           "N max", relN.max())
+    # float32 evaluation of exponentially sensitive Planck factors: y up to 80 amplifies
+    # relative input rounding by y; 2e-4 bounds 80 * (a few float32 ulps)
+    assert np.quantile(relF, 0.99) < 2e-5
+    assert relF_c.max() < 2e-4
+    assert relN.max() < 2e-4
+    np.testing.assert_allclose(eps, eo, rtol=2e-6)
