@@ -33,11 +33,13 @@ struct Carver {
 };
 
 struct Layout {
+    bool pairs = false;
     int n_lines = 0, nseg = 0;
     int64_t total_slots = 0;
     int32_t n_cells = 0, n_nodes = 0, max_nodes = 0;
     int64_t table_floats = 0;
     int32_t n_layer = 0;
+    int32_t photon_region = 0;   // photon records per append region
 };
 
 }  // namespace
@@ -70,12 +72,14 @@ struct pic1d_state {
     long long *pair_sum = nullptr, *n_sum = nullptr, *avg_count = nullptr;
     float4* nodes = nullptr;
     double* rc_nodes = nullptr;
-    float* table = nullptr;
+    float4* table = nullptr;
     int32_t *layer_cell = nullptr, *layer_line = nullptr, *layer_target = nullptr;
     unsigned long long* counters = nullptr;
     DevScalars* sc = nullptr;
     unsigned long long* rho = nullptr;
     double* mom_out = nullptr;
+    PhotonRec* photons = nullptr;
+    int32_t* n_photons = nullptr;
     // per-kernel event timing (pic1d_profile)
     int prof_on = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -107,15 +111,18 @@ hipError_t copy_sync(hipStream_t s, void* dst, const void* src, size_t bytes, hi
         if (e_ != hipSuccess) return fail((st), PIC1D_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+bool c_pairs(const Layout& L) { return L.pairs; }
+
 Layout plan_layout(const pic1d_config* c, std::vector<LineHost>* lines_out) {
     Layout L;
+    L.pairs = c->pairs != 0;
     L.n_lines = c->n_lines;
     L.nseg = 4 * c->n_lines;
     int32_t cb = 0;
     int64_t toff = 0;
     for (int l = 0; l < c->n_lines; ++l) {
         LineHost lh;
-        build_line(c, l, cb, (int32_t)toff, lh);
+        build_line(c, l, cb, (int32_t)(toff / 4), lh);
         cb += c->lines[l].n_cells;
         L.max_nodes = std::max(L.max_nodes, c->lines[l].n_cells + 1);
         for (int s = 0; s < 4; ++s) L.total_slots += lh.cap[s];
@@ -125,6 +132,9 @@ Layout plan_layout(const pic1d_config* c, std::vector<LineHost>* lines_out) {
     }
     L.n_cells = cb;
     L.n_nodes = cb + c->n_lines;
+    // photon records: up to a quarter of all particle slots per step (one event per lepton-step at most)
+    L.photon_region = (int32_t)std::min<int64_t>(std::max<int64_t>(256, (L.total_slots / 4 + PHOTON_REPL - 1) / PHOTON_REPL),
+                                                 (1ll << 30) / PHOTON_REPL);
     L.table_floats = toff;
     return L;
 }
@@ -162,14 +172,16 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->avg_count = cv.take<long long>(1);
     s->nodes = cv.take<float4>(L.n_nodes);
     s->rc_nodes = cv.take<double>(L.n_nodes);
-    s->table = cv.take<float>(std::max<int64_t>(L.table_floats, 1));
+    s->table = cv.take<float4>(std::max<int64_t>(L.table_floats / 4, 1));
     s->layer_cell = cv.take<int32_t>(std::max(L.n_layer, 1));
     s->layer_line = cv.take<int32_t>(std::max(L.n_layer, 1));
     s->layer_target = cv.take<int32_t>(std::max(L.n_layer, 1));
-    s->counters = cv.take<unsigned long long>(NCOUNT * (size_t)L.n_lines);
+    s->counters = cv.take<unsigned long long>((size_t)NCOUNT * CNT_REPL * L.n_lines);
     s->sc = cv.take<DevScalars>(1);
     s->rho = cv.take<unsigned long long>(L.max_nodes);
     s->mom_out = cv.take<double>(8);
+    s->photons = cv.take<PhotonRec>(c_pairs(L) ? (size_t)PHOTON_REPL * L.photon_region : 1);
+    s->n_photons = cv.take<int32_t>(PHOTON_REPL);
 }
 
 PushArgs push_args(pic1d_state* st) {
@@ -185,19 +197,17 @@ PushArgs push_args(pic1d_state* st) {
     a.table = st->table; a.hist[0] = st->hist[0]; a.hist[1] = st->hist[1];
     a.pair_step = st->pair_step; a.counters = st->counters; a.sc = st->sc;
     a.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); a.key1 = (uint32_t)(st->cfg.seed >> 32);
-    const double mr = st->cfg.mass_ratio;
-    const double sign[4] = {-1.0, 1.0, -1.0, 1.0};
-    const double mass[4] = {1.0, 1.0, 1.0, mr};
-    for (int s = 0; s < 4; ++s) {
-        a.sign[s] = sign[s];
-        a.qm[s] = (float)(sign[s] / mass[s]);
-        a.inv_mass[s] = (float)(1.0 / mass[s]);
-    }
+    a.qm_ion = (float)(1.0 / st->cfg.mass_ratio);
+    a.inv_mass_ion = (float)(1.0 / st->cfg.mass_ratio);
+    a.photons = st->photons;
+    a.n_photons = st->n_photons;
+    a.photon_region = st->lay.photon_region;
     return a;
 }
 
 BookArgs book_args(pic1d_state* st) {
     BookArgs b{};
+    b.n_photons = st->n_photons;
     b.n_cur = st->n_cur; b.alloc = st->alloc; b.seg_cap = st->seg_cap; b.tile_prefix = st->tile_prefix;
     b.nseg = st->lay.nseg; b.sc = st->sc;
     return b;
@@ -339,7 +349,9 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     }
     st->n_cu = prop.multiProcessorCount;
     int occ = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_push<RICS_TABLE>, PUSH_TPB, 0);
+    const void* kp = st->backend == RICS_OFF ? (const void*)k_push<RICS_OFF>
+                   : st->backend == RICS_EXACT ? (const void*)k_push<RICS_EXACT> : (const void*)k_push<RICS_TABLE>;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, PUSH_TPB, 0);
     occ = std::max(1, std::min(occ, 8));
     st->push_blocks = st->n_cu * occ;
     st->aux_blocks = st->n_cu * 4;
@@ -437,6 +449,20 @@ int pic1d_step(pic1d_state* st, int32_t n_steps) {
     for (int32_t i = 0; i < n_steps; ++i) {
         int rc = launch_push(st);
         if (rc) return rc;
+        if (st->cfg.pairs) {
+            ConvertArgs ca{};
+            const int b = st->cur;
+            ca.cell = st->cell[b]; ca.off = st->off[b]; ca.u = st->u[b]; ca.id = st->id[b];
+            ca.seg_base = st->seg_base; ca.seg_cap = st->seg_cap; ca.alloc = st->alloc; ca.lines = st->dlines;
+            ca.rc_nodes = st->rc_nodes; ca.hist[0] = st->hist[0]; ca.hist[1] = st->hist[1];
+            ca.pair_step = st->pair_step; ca.counters = st->counters; ca.sc = st->sc;
+            ca.photons = st->photons; ca.n_photons = st->n_photons; ca.photon_region = st->lay.photon_region;
+            ca.conversion = st->cfg.conversion;
+            ca.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); ca.key1 = (uint32_t)(st->cfg.seed >> 32);
+            const int pk = prof_begin(st, 5);
+            hipLaunchKernelGGL(k_convert, dim3(PHOTON_REPL), dim3(256), 0, st->stream, ca);
+            prof_end(st, pk);
+        }
         if (st->cfg.atmosphere && st->lay.n_layer > 0) {
             AtmArgs a{};
             const int b = st->cur;
@@ -509,12 +535,12 @@ int pic1d_moments(pic1d_state* st, int32_t line, int32_t flags, pic1d_moments_ou
     DevScalars sc{};
     long long avg = 0;
     std::vector<int32_t> ncur(4);
-    std::vector<unsigned long long> cnt(NCOUNT);
+    std::vector<unsigned long long> cnt((size_t)NCOUNT * CNT_REPL);
     HIP_TRY(st, hipMemcpyAsync(mo, st->mom_out, sizeof(mo), hipMemcpyDeviceToHost, s));
     HIP_TRY(st, hipMemcpyAsync(&sc, st->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
     HIP_TRY(st, hipMemcpyAsync(&avg, st->avg_count, sizeof(avg), hipMemcpyDeviceToHost, s));
     HIP_TRY(st, hipMemcpyAsync(ncur.data(), st->n_cur + 4 * line, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(st, hipMemcpyAsync(cnt.data(), st->counters + NCOUNT * line, NCOUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(st, hipMemcpyAsync(cnt.data(), st->counters + (size_t)NCOUNT * CNT_REPL * line, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     const bool average = (flags & PIC1D_MOM_AVERAGE) != 0;
     std::vector<int32_t> hist(4 * (size_t)n);
     std::vector<long long> nsum, psum;
@@ -554,7 +580,10 @@ int pic1d_moments(pic1d_state* st, int32_t line, int32_t flags, pic1d_moments_ou
     for (int k = 0; k < 4; ++k) out->count[k] = 0;
     out->step = (int64_t)sc.step;
     out->avg_steps = avg;
-    for (int k = 0; k < NCOUNT; ++k) out->counters[k] = (int64_t)cnt[k];
+    for (int k = 0; k < NCOUNT; ++k) {
+        out->counters[k] = 0;
+        for (int r = 0; r < CNT_REPL; ++r) out->counters[k] += (int64_t)cnt[(size_t)r * NCOUNT + k];
+    }
     // live counts: the histogram of the current particles (absorbed ones excluded)
     {
         std::vector<int32_t> hc(4 * (size_t)n);

@@ -8,8 +8,23 @@ namespace pic1d {
 enum { RICS_OFF = 0, RICS_EXACT = 1, RICS_TABLE = 2, RICS_MLP = 3 };
 
 constexpr int PUSH_TPB = 256;                   // threads per block of the particle kernels
-constexpr int PUSH_PPT = 4;                     // particles per thread per tile
-constexpr int PUSH_TILE = PUSH_TPB * PUSH_PPT;  // particles per tile
+constexpr int PUSH_PPT = 8;                     // consecutive particles per thread per tile
+constexpr int CNT_REPL = 64;                    // replicas of every counter (spreads same-address atomics)
+constexpr int PUSH_TILE = 64 * PUSH_PPT;        // particles per tile: one wavefront's work item
+constexpr int AUX_PPT = PUSH_TILE / PUSH_TPB;   // particles per thread when a block takes a tile
+
+constexpr int PHOTON_REPL = 64;                 // append regions of the photon buffer
+
+// A photon above the pair threshold, recorded by the pusher for the conversion kernel.
+struct PhotonRec {
+    uint64_t pid;     // emitting lepton
+    int32_t line;
+    int32_t cell;     // emission point: cell and offset (x^n)
+    float off;
+    float u_pre;      // lepton momentum before the recoil (sets gamma and eps)
+    float b;          // B / B_QED at the emission point
+    float dir;        // direction of emission (+1 / -1 along s)
+};
 
 struct PushArgs {
     int32_t* cell;
@@ -29,18 +44,38 @@ struct PushArgs {
     unsigned long long* J;
     const float4* nodes;
     const double* rc_nodes;
-    const float* table;
+    const float4* table;       // RICS tables, [line][ns][nlg] {F(i), F(i+1), Ndot(i), Ndot(i+1)}
     int32_t* hist[2];          // per-cell counts, ping-pong by step parity
-    const int32_t* hist_in;    // set in the kernel: counts at the start of the step
-    int32_t* hist_out;         // set in the kernel: counts of the new positions
     int32_t* pair_step;
-    unsigned long long* counters;   // [line][8]
+    unsigned long long* counters;   // [line][CNT_REPL][NCOUNT]
     DevScalars* sc;
-    uint64_t step;             // set in the kernel from sc->step
     uint32_t key0, key1;
-    float qm[4];               // charge / mass per species (units of e/m_e)
-    double sign[4];            // charge sign per species
-    float inv_mass[4];         // m_e / m per species
+    float qm_ion;              // charge / mass of an ion (units of e/m_e)
+    float inv_mass_ion;        // m_e / m_i
+    PhotonRec* photons;        // PHOTON_REPL regions of photon_region slots
+    int32_t* n_photons;        // [PHOTON_REPL] fill of each region
+    int32_t photon_region;
+};
+
+struct ConvertArgs {
+    int32_t* cell;
+    float* off;
+    float* u;
+    uint64_t* id;
+    const int64_t* seg_base;
+    const int32_t* seg_cap;
+    int32_t* alloc;
+    const LineDev* lines;
+    const double* rc_nodes;
+    int32_t* hist[2];
+    int32_t* pair_step;
+    unsigned long long* counters;
+    DevScalars* sc;
+    const PhotonRec* photons;
+    const int32_t* n_photons;
+    int32_t photon_region;
+    int32_t conversion;
+    uint32_t key0, key1;
 };
 
 struct AtmArgs {
@@ -64,6 +99,7 @@ struct AtmArgs {
 };
 
 struct BookArgs {
+    int32_t* n_photons;        // reset to 0 for the next step (may be null)
     int32_t* n_cur;
     int32_t* alloc;
     const int32_t* seg_cap;
@@ -156,6 +192,7 @@ struct MomArgs {
 
 template <int BACKEND> __global__ void k_push(PushArgs a);
 __global__ void k_atmosphere(AtmArgs a);
+__global__ void k_convert(ConvertArgs a);
 __global__ void k_plan(BookArgs b, int advance_step);
 __global__ void k_field(FieldArgs f);
 __global__ void k_sort_scan(SortArgs s);

@@ -47,6 +47,27 @@ __device__ __forceinline__ int find_segment(const int32_t* __restrict__ prefix, 
 
 // XCD-aware tile walk: the 8 XCDs each take a contiguous range of tiles (blocks
 // are dispatched round-robin over XCDs, so block b runs on XCD b % 8).
+// Same walk at wavefront granularity: wavefront w of block b takes tile slots of
+// its XCD's range.
+struct WaveWalk {
+    int t, end, stride;
+    __device__ WaveWalk(int total) {
+        const int wpb = blockDim.x >> 6;
+        const int nb = gridDim.x >> 3;
+        // wave-uniform: keeps every per-tile quantity in scalar registers
+        const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        if (nb == 0 || (gridDim.x & 7) != 0) {
+            t = blockIdx.x * wpb + wid; end = total; stride = gridDim.x * wpb;
+            return;
+        }
+        const int x = blockIdx.x & 7, lw = (blockIdx.x >> 3) * wpb + wid;
+        const int chunk = (total + 7) >> 3;
+        t = x * chunk + lw;
+        end = min(total, (x + 1) * chunk);
+        stride = nb * wpb;
+    }
+};
+
 struct TileWalk {
     int t, end, stride;
     __device__ TileWalk(int total) {
@@ -60,59 +81,117 @@ struct TileWalk {
     }
 };
 
-__device__ __forceinline__ Geo geo_at(const float4* __restrict__ nodes, int node, float f) {
+// Geometry of a particle at cell c0, offset f: linear between the two nodes.
+__device__ __forceinline__ Geo geo_lerp(const LineDev& L, const float4& a, const float4& b, float f) {
+    Geo g;
+    g.b = fmaf(f, b.x - a.x, a.x);
+    g.mu = fmaf(f, b.y - a.y, a.y);
+    const float xr = fmaf(f, b.z - a.z, a.z);
+    g.ix2 = frcp(xr * xr);
+    g.by = g.b * L.inv_theta;
+    return g;
+}
+
+__device__ __forceinline__ Geo geo_at(const LineDev& L, const float4* __restrict__ nodes, int node, float f) {
     const float4 a = nodes[node];
     const float4 b = nodes[node + 1];
     Geo g;
     g.b = fmaf(f, b.x - a.x, a.x);
     g.mu = fmaf(f, b.y - a.y, a.y);
-    g.xr = fmaf(f, b.z - a.z, a.z);
-    g.rc = fmaf(f, b.w - a.w, a.w);
+    const float xr = fmaf(f, b.z - a.z, a.z);
+    g.ix2 = frcp(xr * xr);
+    g.by = g.b * L.inv_theta;
     return g;
 }
 
+// What the RICS evaluations of one particle share: its geometry and (table
+// backend) its table rows.
+struct PartGeo {
+    Geo g;
+    TabRows rows;
+};
+
+template <int BACKEND, bool DF>
+__device__ __forceinline__ float rics_F(const PushArgs& a, const LineDev& L, float u, const PartGeo& pg, float& dF) {
+    if constexpr (BACKEND == RICS_TABLE) return table_F<DF>(L, a.table + L.table_off, a.nlg, pg.rows, u, dF);
+    else return exact_F<DF>(L, u, pg.g, dF);
+}
+
 template <int BACKEND>
-__device__ __forceinline__ RicsOut rics_eval(const PushArgs& a, const LineDev& L, float u, const Geo& g,
-                                             int c0, float o0) {
-    if constexpr (BACKEND == RICS_TABLE) {
-        double x = (double)c0 + (double)o0;
-        if (u < 0.0f) x = (double)L.n_cells - x;
-        return rics_table(L, a.table + L.table_off, a.nlg, a.ns, u, x);
-    } else {
-        return rics_exact(L, u, g);
+__device__ __forceinline__ float rics_N(const PushArgs& a, const LineDev& L, float u, const PartGeo& pg) {
+    if constexpr (BACKEND == RICS_TABLE) return table_N(L, a.table + L.table_off, a.nlg, pg.rows, u);
+    else return exact_N(L, u, pg.g);
+}
+
+template <int BACKEND>
+__device__ __forceinline__ PartGeo part_geo(const LineDev& L, const float4& n0, const float4& n1, float o0, double x,
+                                            int ns) {
+    PartGeo pg;
+    pg.g = geo_lerp(L, n0, n1, o0);
+    if constexpr (BACKEND == RICS_TABLE) pg.rows = table_rows(L, ns, x);
+    return pg;
+}
+
+// Newton-Raphson on u1 - u0 - (h/4)(F(u0) + F(u1)) = 0 from the explicit start
+// (kept out of line: it is rarely needed at these step sizes).
+template <int BACKEND>
+__device__ __forceinline__ float newton_midpoint(const PushArgs& a, const LineDev& L, float u0, float F0, float u1,
+                                              const PartGeo& g) {
+    const float hq = 0.25f * L.h;
+#pragma unroll 1
+    for (int it = 0; it < 4; ++it) {
+        float dF1;
+        const float F1 = rics_F<BACKEND, true>(a, L, u1, g, dF1);
+        const float G = u1 - u0 - hq * (F0 + F1);
+        const float del = G / (1.0f - hq * dF1);
+        u1 -= del;
+        if (fabsf(del) <= 0x1.0p-24f * fabsf(u1)) break;
     }
+    return u1;
+}
+
+template <int BACKEND>
+__device__ __forceinline__ bool needs_newton(const PushArgs& a, const LineDev& L, float u0, float F0, float u1,
+                                          const PartGeo& g) {
+    float dF0;
+    (void)rics_F<BACKEND, true>(a, L, u0, g, dF0);
+    return 0.25f * L.h * fabsf(dF0) * 0.5f * L.h * fabsf(F0) > 0x1.0p-25f * fabsf(u1);
 }
 
 // One drag update over h/2 (Sec. 3): implicit midpoint where |F(p0)| tau_min <= |p0|,
-// solved by Newton from the explicit start p0 + (h/2) F(p0) and stopped once the
-// step falls below float32 resolution; exponential relaxation towards
-// p_tilde = mu / (1 - mu^2)^(1/2) otherwise.
+// solved by Newton from the explicit start p0 + (h/2) F(p0) -- needed only when
+// the predicted correction (h/4)|F'|(h/2)|F0| exceeds half an ulp of the result --
+// and exponential relaxation towards p_tilde = mu / (1 - mu^2)^(1/2) otherwise.
 template <int BACKEND>
-__device__ __forceinline__ float drag_half(const PushArgs& a, const LineDev& L, float u0, const Geo& g,
-                                           int c0, float o0, int& n_limited, int& n_newton) {
-    const RicsOut r0 = rics_eval<BACKEND>(a, L, u0, g, c0, o0);
-    if (fabsf(r0.F) * L.tau_hat <= fabsf(u0)) {
-        const float hq = 0.25f * L.h;
-        float u1 = fmaf(0.5f * L.h, r0.F, u0);
-        // predicted Newton correction of the explicit start: (h/4)|F'| (h/2)|F0|
-        if (hq * fabsf(r0.dF) * 0.5f * L.h * fabsf(r0.F) > 0x1.0p-25f * fabsf(u1)) {
-            ++n_newton;
-#pragma unroll 1
-            for (int it = 0; it < 4; ++it) {
-                const RicsOut r1 = rics_eval<BACKEND>(a, L, u1, g, c0, o0);
-                const float G = u1 - u0 - hq * (r0.F + r1.F);
-                const float dG = 1.0f - hq * r1.dF;
-                const float del = G / dG;
-                u1 -= del;
-                if (fabsf(del) <= 0x1.0p-24f * fabsf(u1)) break;
-            }
+__device__ __forceinline__ float drag_half(const PushArgs& a, const LineDev& L, float u0, const PartGeo& g,
+                                           float ptilde, bool alive, int& n_limited, int& n_newton) {
+    float unused;
+    const float F0 = rics_F<BACKEND, false>(a, L, u0, g, unused);
+    if (fabsf(F0) * L.tau_hat <= fabsf(u0)) {
+        float u1 = fmaf(0.5f * L.h, F0, u0);
+        // |(h/2) F0| <= |u0| h / (2 tau_min): below float32 resolution of the Newton
+        // correction whenever (h/2) |F0| itself is tiny; otherwise ask the derivative
+        if (F0 != 0.0f && 0.5f * L.h * fabsf(F0) > 0x1.0p-12f * fabsf(u0) &&
+            needs_newton<BACKEND>(a, L, u0, F0, u1, g)) {
+            n_newton += alive ? 1 : 0;
+            u1 = newton_midpoint<BACKEND>(a, L, u0, F0, u1, g);
         }
         return u1;
     }
-    ++n_limited;
-    const float pt = g.mu * rsqrtf(fmaxf(fmaf(-g.mu, g.mu, 1.0f), 1e-30f));
-    return fmaf(-(u0 - pt), L.damp, u0);
+    n_limited += alive ? 1 : 0;
+    return fmaf(-(u0 - ptilde), L.damp, u0);
 }
+
+// Per-tile constants of the pusher (species of the tile, step, count buffers).
+struct TileCtx {
+    uint64_t step;
+    const int32_t* hist_in;     // counts at the start of the step
+    int32_t* hist_out;          // counts of the new positions
+    float qm;                   // charge / mass of the species (units of e/m_e)
+    float inv_mass;             // m_e / m
+    bool negative;              // negative charge
+    bool gravity;               // the tile touches an atmosphere layer
+};
 
 // Append one particle to a segment; returns false (and flags ECAPACITY) if full.
 __device__ __forceinline__ bool append_particle(const PushArgs& a, int seg, int cell, float off, float u,
@@ -135,269 +214,435 @@ struct Counts {
         draws = 0;
 };
 
-// Everything one particle does in one step.  Returns its new cell (DEAD_CELL if it
-// left the line) and writes the deposit contributions (cell, fixed-point value).
+// Stochastic regime (b >= b_thr, Sec. 3): after the kick, a scattering event with
+// probability min(Ndot h, 1) from the Philox draw keyed by (step, id); the event
+// emits eps = gamma (1 - (1+2b)^-1/2) and leaves gamma / (1+2b)^1/2 (Appendix A).
 template <int BACKEND>
-__device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDev& L, int line, int sp,
-                                                 int64_t k, int c0, Counts& cnt, int& ca, long long& da,
-                                                 int& cb, long long& db, int& cnew) {
-    const int n = L.n_cells;
-    const float o0 = a.off[k];
-    float u = a.u[k];
-
-    // field gather: E at x^n, linear between cell centres, constant beyond the outer ones
-    double Ep;
-    {
-        int kk;
-        float w;
-        if (o0 >= 0.5f) { kk = c0; w = o0 - 0.5f; } else { kk = c0 - 1; w = o0 + 0.5f; }
-        const double* E = a.E + L.cell_base;
-        if (kk < 0) Ep = E[0];
-        else if (kk >= n - 1) Ep = E[n - 1];
-        else Ep = fma((double)w, E[kk + 1] - E[kk], E[kk]);
-    }
-    float kick = a.qm[sp] * (float)Ep * L.invC;
-    if (a.gravity) {
-        const double x = (double)c0 + (double)o0;
-        const double dw = fmin(x, (double)n - x);
-        if (dw <= (double)L.atm_depth) kick += ((x < (double)L.half_n) ? -1.0f : 1.0f) * L.grav * a.inv_mass[sp];
-    }
-
-    if (BACKEND != RICS_OFF && sp != 3) {
-        const Geo g = geo_at(a.nodes, L.node_base + c0, o0);
-        if (g.b < L.b_thr) {
-            // continuous regime: Strang splitting drag h/2, Lorentz kick, drag h/2
-            u = drag_half<BACKEND>(a, L, u, g, c0, o0, cnt.limited, cnt.newton);
-            u += kick;
-            u = drag_half<BACKEND>(a, L, u, g, c0, o0, cnt.limited, cnt.newton);
+__device__ __forceinline__ float stochastic_step(const PushArgs& a, const LineDev& L, const TileCtx& T, int line,
+                                              int64_t k, int c0, float o0, float u, const PartGeo& pg,
+                                              Counts& cnt) {
+    const Geo& g = pg.g;
+    const float lam = rics_N<BACKEND>(a, L, u, pg) * L.h;
+    if (lam > 1.0f) ++cnt.clipped;
+    if (!(lam > 0.0f)) return u;
+    ++cnt.draws;
+    const uint64_t pid = a.id[k];
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)T.step, (uint32_t)pid, (uint32_t)(pid >> 32), STREAM_RICS),
+                                  a.key0, a.key1);
+    if (!(uniform24(w.x) < fminf(lam, 1.0f))) return u;
+    ++cnt.events;
+    const float gam = fsqrt(fmaf(u, u, 1.0f));
+    const float dir = (u >= 0.0f) ? 1.0f : -1.0f;
+    const float eps = photon_energy(gam, g.b);
+    const float gnew = gam * frsq(fmaf(2.0f, g.b, 1.0f));
+    const float u_pre = u;
+    u = dir * fsqrt(fmaxf((gnew - 1.0f) * (gnew + 1.0f), 0.0f));
+    if (a.pairs && eps >= 2.0f) {
+        // record for the conversion kernel; lanes of a wavefront reserve their slots together
+        const unsigned long long m = __ballot(1);
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((long long)m) - 1;
+        const int r = blockIdx.x & (PHOTON_REPL - 1);
+        int slot0 = 0;
+        if (lane == leader) slot0 = atomicAdd(&a.n_photons[r], __popcll(m));
+        const int slot = __shfl(slot0, leader, 64) + __popcll(m & ((1ull << lane) - 1ull));
+        if (slot < a.photon_region) {
+            PhotonRec& p = a.photons[(size_t)r * a.photon_region + slot];
+            p.pid = pid;
+            p.line = line;
+            p.cell = c0;
+            p.off = o0;
+            p.u_pre = u_pre;
+            p.b = g.b;
+            p.dir = dir;
         } else {
-            // stochastic regime: kick, then a scattering event with probability min(Ndot h, 1)
+            set_error(&a.sc->err, -3);
+        }
+    } else {
+        ++cnt.escaped;
+    }
+    return u;
+}
+
+// Field and geometry of the cell a lane is working in.  A lane's particles are
+// consecutive in cell order, so the cache is reloaded only when the cell changes.
+// The neighbours of E are clamped at the walls, which makes the gather constant
+// beyond the outermost cell centres.
+struct CellCache {
+    int cell;
+    double Em, E0, Ep;      // E at the centres of cells c-1, c, c+1
+    float4 n0, n1;          // geometry nodes c, c+1
+};
+
+template <bool GEO>
+__device__ __forceinline__ void cache_load(CellCache& cc, const PushArgs& a, const LineDev& L, int c0) {
+    cc.cell = c0;
+    const double* E = a.E + L.cell_base;
+    cc.Em = E[max(c0 - 1, 0)];
+    cc.E0 = E[c0];
+    cc.Ep = E[min(c0 + 1, L.n_cells - 1)];
+    if (GEO) {
+        cc.n0 = a.nodes[L.node_base + c0];
+        cc.n1 = a.nodes[L.node_base + c0 + 1];
+    }
+}
+
+// Everything one particle does in one step: gather, RICS, kick, move, and the
+// deposit of its path in fixed point.  Written without data-dependent branches on
+// the common path (dead lanes compute on sanitised inputs and are masked out).
+// Returns the new cell (DEAD_CELL when absorbed) in c1; da goes to the old cell,
+// db to the neighbour the path crossed into (d = c1 - c0 in {-1, 0, 1}).
+template <int BACKEND>
+__device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDev& L, const TileCtx& T,
+                                                 const CellCache& cc, bool alive, int line, int sp, int64_t k,
+                                                 int c0, float o0, float& u, Counts& cnt, int& c1, float& o1,
+                                                 long long& da, long long& db, int& d) {
+    const int n = L.n_cells;
+    constexpr bool RICS = BACKEND != RICS_OFF;
+
+    // field gather: E at x^n, linear between cell centres
+    const bool upper = o0 >= 0.5f;
+    const double Ea = upper ? cc.E0 : cc.Em;
+    const double Eb = upper ? cc.Ep : cc.E0;
+    const float w = upper ? o0 - 0.5f : o0 + 0.5f;
+    float kick = T.qm * (float)fma((double)w, Eb - Ea, Ea) * L.invC;
+    const double x = (double)c0 + (double)o0;
+    if (T.gravity) {
+        const double dw = fmin(x, (double)n - x);
+        const float gk = ((x < (double)L.half_n) ? -1.0f : 1.0f) * L.grav * T.inv_mass;
+        kick += (dw <= L.atm_depth) ? gk : 0.0f;
+    }
+
+    if (RICS && sp != 3) {
+        const PartGeo pg = part_geo<BACKEND>(L, cc.n0, cc.n1, o0, x, a.ns);
+        if (pg.g.b < L.b_thr) {
+            // continuous regime: Strang splitting drag h/2, Lorentz kick, drag h/2, both
+            // at x^n; the damping branch relaxes towards p_tilde = mu / (1 - mu^2)^(1/2)
+            const float pt = pg.g.mu * frsq(fmaxf(fmaf(-pg.g.mu, pg.g.mu, 1.0f), 1e-30f));
+            u = drag_half<BACKEND>(a, L, u, pg, pt, alive, cnt.limited, cnt.newton);
             u += kick;
-            const RicsOut r = rics_eval<BACKEND>(a, L, u, g, c0, o0);
-            const float lam = r.N * L.h;
-            if (lam > 1.0f) ++cnt.clipped;
-            if (lam > 0.0f) {
-                ++cnt.draws;
-                const uint64_t pid = a.id[k];
-                const uint4 w = philox4x32_10(make_uint4((uint32_t)a.step, (uint32_t)pid, (uint32_t)(pid >> 32),
-                                                         STREAM_RICS), a.key0, a.key1);
-                if (uniform24(w.x) < fminf(lam, 1.0f)) {
-                    ++cnt.events;
-                    const float gam = sqrtf(fmaf(u, u, 1.0f));
-                    const float dir = (u >= 0.0f) ? 1.0f : -1.0f;
-                    const float eps = photon_energy(gam, g.b);
-                    const float gnew = gam / sqrtf(fmaf(2.0f, g.b, 1.0f));
-                    const float u_pre = u;
-                    u = dir * sqrtf(fmaxf((gnew - 1.0f) * (gnew + 1.0f), 0.0f));
-                    // photon conversion into an e-/e+ pair (Sec. 3), limited by n_max
-                    bool made = false;
-                    if (a.pairs && eps >= 2.0f) {
-                        int cs;
-                        float os;
-                        bool ok;
-                        if (a.conversion == 0) {
-                            cs = c0; os = o0; ok = true;
-                        } else {
-                            // eps in float64 from the post-kick momentum on this rare path
-                            const double ud = (double)u_pre;
-                            const double epsd = sqrt(1.0 + ud * ud) * (1.0 - 1.0 / sqrt(1.0 + 2.0 * (double)g.b));
-                            const double rc = fma((double)o0, a.rc_nodes[L.node_base + c0 + 1] - a.rc_nodes[L.node_base + c0],
-                                                  a.rc_nodes[L.node_base + c0]);
-                            const double sp_ = (double)c0 + (double)o0 +
-                                               (double)dir * rc * L.inv_ds * asin(fmin(2.0 / epsd, 1.0));
-                            ok = (sp_ >= 0.0) && (sp_ < (double)n);
-                            cs = ok ? (int)floor(sp_) : 0;
-                            os = ok ? (float)(sp_ - (double)cs) : 0.0f;
-                            if (os >= 1.0f) { os = 0.0f; cs += 1; ok = ok && cs < n; }
-                        }
-                        if (ok) {
-                            const int* hc = a.hist_in + 4 * (size_t)(L.cell_base + cs);
-                            const int tot = hc[0] + hc[1] + hc[2] + hc[3];
-                            if ((float)tot < L.nmax) {
-                                // pair members at gamma = eps/2 each, in float64 on this rare path
-                                // (u is ill-conditioned in eps when eps/2 is close to 1)
-                                const double ud = (double)u_pre;
-                                const double gpd = 0.5 * sqrt(1.0 + ud * ud) * (2.0 * (double)g.b) /
-                                                   (sqrt(1.0 + 2.0 * (double)g.b) * (1.0 + sqrt(1.0 + 2.0 * (double)g.b)));
-                                const float up = dir * (float)sqrt(fmax((gpd - 1.0) * (gpd + 1.0), 0.0));
-                                const uint64_t pid = a.id[k];
-                                const uint4 wc = philox4x32_10(make_uint4((uint32_t)a.step, (uint32_t)pid,
-                                                                          (uint32_t)(pid >> 32), STREAM_CHILD),
-                                                               a.key0, a.key1);
-                                const bool e_ok = append_particle(a, 4 * line + 0, cs, os, up, id_from_words(wc.x, wc.y));
-                                const bool p_ok = append_particle(a, 4 * line + 1, cs, os, up, id_from_words(wc.z, wc.w));
-                                if (e_ok && p_ok) {
-                                    int* ho = a.hist_out + 4 * (size_t)(L.cell_base + cs);
-                                    atomicAdd(&ho[0], 1);
-                                    atomicAdd(&ho[1], 1);
-                                    atomicAdd(&a.pair_step[L.cell_base + cs], 1);
-                                    ++cnt.pairs;
-                                    made = true;
-                                }
-                            }
-                        }
-                    }
-                    if (!made) ++cnt.escaped;
-                }
-            }
+            u = drag_half<BACKEND>(a, L, u, pg, pt, alive, cnt.limited, cnt.newton);
+        } else {
+            u += kick;
+            if (alive) u = stochastic_step<BACKEND>(a, L, T, line, k, c0, o0, u, pg, cnt);
         }
     } else {
         u += kick;
     }
-    if (!isfinite(u)) set_error(&a.sc->err, -5);
+    if (alive && !isfinite(u)) set_error(&a.sc->err, -5);
 
     // move x^{n+1} = x^n + C u / gamma with the offset carried into the cell index
-    const float gam = sqrtf(fmaf(u, u, 1.0f));
-    const float dx = L.C * u / gam;
-    float o1 = o0 + dx;
-    int c1 = c0;
-    if (o1 >= 1.0f) {
-        o1 -= 1.0f;
-        c1 += 1;
-    } else if (o1 < 0.0f) {
-        o1 += 1.0f;
-        c1 -= 1;
-        if (o1 >= 1.0f) { o1 = 0.0f; c1 += 1; }
-    }
-    // charge-conserving deposit of the path [x^n, x^{n+1}] clipped to [0, n],
-    // from the stored old and new positions (exact in float64)
-    ca = c0;
-    cb = -1;
-    db = 0;
-    double va, vb = 0.0;
-    if (c1 == c0) {
-        va = (double)o1 - (double)o0;
-    } else if (c1 > c0) {
-        va = 1.0 - (double)o0;
-        cb = c1;
-        vb = (double)o1;
-    } else {
-        va = -(double)o0;
-        cb = c1;
-        vb = (double)o1 - 1.0;
-    }
-    const double qs = a.sign[sp] * FIX_SCALE;
-    da = __double2ll_rn(va * qs);
-    if (cb >= 0 && cb < n) db = __double2ll_rn(vb * qs); else cb = -1;
-
-    if (c1 < 0 || c1 >= n) {
-        ++cnt.absorbed;
-        cnew = DEAD_CELL;
-        a.cell[k] = DEAD_CELL;
-    } else {
-        cnew = c1;
-        a.cell[k] = c1;
-        a.off[k] = o1;
-    }
-    a.u[k] = u;
+    o1 = fmaf(L.C * u, frsq(fmaf(u, u, 1.0f)), o0);
+    const int up = o1 >= 1.0f, dn = o1 < 0.0f;
+    o1 = o1 - (float)up + (float)dn;          // exact for o1 in [1, 1.5); o1 + 1 may round up to 1
+    const int fix = o1 >= 1.0f;
+    o1 = fix ? 0.0f : o1;
+    d = up - dn + fix;
+    c1 = c0 + d;
+    // fixed-point deposit (units of 2^-32 cell) of the path, from the stored old and new
+    // offsets quantised to that grid: differences of quantised positions telescope,
+    // so the deposit equals the change of the quantised charge density exactly
+    const long long f0 = (long long)__float2uint_rn(o0 * 4294967296.0f);
+    const long long f1 = (long long)__float2uint_rn(o1 * 4294967296.0f);
+    da = (d == 0) ? f1 - f0 : ((d > 0) ? 4294967296ll - f0 : -f0);
+    db = (d > 0) ? f1 : ((d < 0) ? f1 - 4294967296ll : 0ll);
+    if (c1 < 0 || c1 >= n) db = 0;            // the part of the path beyond a wall is not deposited
+    if (T.negative) { da = -da; db = -db; }
+    const bool gone = c1 < 0 || c1 >= n;
+    cnt.absorbed += (alive && gone) ? 1 : 0;
+    c1 = gone ? DEAD_CELL : c1;
 }
 
-__device__ void flush_counts(const PushArgs& a, int line, Counts& c) {
-    int v[9] = {c.events, c.pairs, c.escaped, c.absorbed, c.clipped, c.limited, c.newton, c.pushed, c.draws};
+__device__ __forceinline__ void counts_flush(unsigned long long* counters, int line, Counts& c) {
+    const int v[9] = {c.events, c.pairs, c.escaped, c.absorbed, c.clipped, c.limited, c.newton, c.pushed, c.draws};
     const int slot[9] = {0, 1, 2, 3, 4, 5, 6, 8, 9};
+    const size_t rep = ((size_t)line * CNT_REPL + (blockIdx.x & (CNT_REPL - 1))) * NCOUNT;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int s = wave_sum_i(v[i]);
-        if ((threadIdx.x & 63) == 0 && s != 0)
-            atomicAdd(&a.counters[line * NCOUNT + slot[i]], (unsigned long long)s);
+        if ((threadIdx.x & 63) == 0 && s != 0) atomicAdd(&counters[rep + slot[i]], (unsigned long long)s);
     }
     c = Counts();
 }
 
-constexpr int WMAX = 384;     // LDS window of the deposit, cells
-constexpr int NCOPY = 4;      // privatised copies of the window (fewer same-address LDS atomics)
+constexpr int WW = 256;     // deposit window of one wavefront, cells
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The particle kernel.  Work is split into tiles of PUSH_TILE consecutive particles
+// of one (line, species) segment, one tile per wavefront at a time, PUSH_PPT
+// consecutive particles per lane (128-bit loads and stores).  Each lane
+// accumulates its deposit and new-cell counts over runs of particles in the same
+// cell (three cells wide: the run's cell and its neighbours); each wavefront
+// merges its lanes in a private LDS window and flushes the window to the global
+// fixed-point current with one atomic per touched cell.  No block-level
+// synchronisation.
 template <int BACKEND>
 __global__ __launch_bounds__(PUSH_TPB) void k_push(PushArgs a) {
-    __shared__ unsigned long long sJ[NCOPY][WMAX];
-    __shared__ int sH[WMAX];
-    __shared__ int sRed[2][PUSH_TPB / 64];
+    __shared__ unsigned long long sJ[PUSH_TPB / 64][WW];
+    __shared__ int sH[PUSH_TPB / 64][WW];
     if (a.sc->err != 0) return;
-    a.step = a.sc->step;
-    a.hist_in = a.hist[a.step & 1];
-    a.hist_out = a.hist[(a.step & 1) ^ 1];
+    constexpr bool GEO = BACKEND != RICS_OFF;
+    const uint64_t step = a.sc->step;
+    const int32_t* hist_in = (step & 1) ? a.hist[1] : a.hist[0];
+    int32_t* hist_out = (step & 1) ? a.hist[0] : a.hist[1];
     const int total = a.tile_prefix[a.nseg];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int copy = lane & (NCOPY - 1);
-    for (TileWalk tw(total); tw.t < tw.end; tw.t += tw.stride) {
-        const int t = tw.t;
-        const int seg = find_segment(a.tile_prefix, a.nseg, t);
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    Counts cnt;
+    int cur_line = -1;
+    int seg = 0, seg_t0 = 0, seg_t1 = 0;       // segment of the previous tile and its tile range
+    for (WaveWalk ww(total); ww.t < ww.end; ww.t += ww.stride) {
+        const int t = ww.t;
+        if (t < seg_t0 || t >= seg_t1) {
+            seg = find_segment(a.tile_prefix, a.nseg, t);
+            seg_t0 = a.tile_prefix[seg];
+            seg_t1 = a.tile_prefix[seg + 1];
+        }
         const int line = seg >> 2, sp = seg & 3;
+        if (line != cur_line) {
+            if (cur_line >= 0) counts_flush(a.counters, cur_line, cnt);
+            cur_line = line;
+        }
         const LineDev L = a.lines[line];
-        const int nseg_cur = a.n_cur[seg];
+        const int ncur = a.n_cur[seg];
         const int64_t base = a.seg_base[seg];
-        const int i0 = (t - a.tile_prefix[seg]) * PUSH_TILE;
-
-        // pass 1: cells of the tile -> window [lo, hi] of cells the deposit can touch
-        int cl[PUSH_PPT];
-        int lo = INT32_MAX, hi = INT32_MIN;
+        // this lane's PUSH_PPT consecutive particles (vector loads; slots up to the
+        // capacity, a multiple of 256, always exist)
+        const int ib = (t - seg_t0) * PUSH_TILE + lane * PUSH_PPT;
+        const int nv = max(0, min(PUSH_PPT, ncur - ib));
+        int c[PUSH_PPT];
+        float o[PUSH_PPT], uu[PUSH_PPT];
+        {
+            const int4* cp = reinterpret_cast<const int4*>(a.cell + base + ib);
+            const float4* op = reinterpret_cast<const float4*>(a.off + base + ib);
+            const float4* up = reinterpret_cast<const float4*>(a.u + base + ib);
 #pragma unroll
-        for (int q = 0; q < PUSH_PPT; ++q) {
-            const int i = i0 + q * PUSH_TPB + threadIdx.x;
-            cl[q] = (i < nseg_cur) ? a.cell[base + i] : DEAD_CELL;
-            if (cl[q] != DEAD_CELL) {
-                lo = min(lo, cl[q] - 1);
-                hi = max(hi, cl[q] + 1);
+            for (int h = 0; h < PUSH_PPT / 4; ++h) {
+                int4 ci = make_int4(DEAD_CELL, DEAD_CELL, DEAD_CELL, DEAD_CELL);
+                float4 oi = make_float4(0.5f, 0.5f, 0.5f, 0.5f), ui = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (nv > 0) { ci = cp[h]; oi = op[h]; ui = up[h]; }
+                c[4 * h + 0] = ci.x; c[4 * h + 1] = ci.y; c[4 * h + 2] = ci.z; c[4 * h + 3] = ci.w;
+                o[4 * h + 0] = oi.x; o[4 * h + 1] = oi.y; o[4 * h + 2] = oi.z; o[4 * h + 3] = oi.w;
+                uu[4 * h + 0] = ui.x; uu[4 * h + 1] = ui.y; uu[4 * h + 2] = ui.z; uu[4 * h + 3] = ui.w;
             }
         }
+        int lo = INT32_MAX, hi = INT32_MIN, first = -1;
+#pragma unroll
+        for (int q = PUSH_PPT - 1; q >= 0; --q) {
+            if (q >= nv) c[q] = DEAD_CELL;
+            if (c[q] != DEAD_CELL) {
+                lo = min(lo, c[q] - 1);
+                hi = max(hi, c[q] + 1);
+                first = c[q];
+            }
+        }
+        // window [lo, hi] of cells this wavefront's deposit can touch
         lo = wave_min_i(lo);
         hi = wave_max_i(hi);
-        if (lane == 0) { sRed[0][wid] = lo; sRed[1][wid] = hi; }
-        __syncthreads();
-        lo = sRed[0][0]; hi = sRed[1][0];
-#pragma unroll
-        for (int w = 1; w < PUSH_TPB / 64; ++w) { lo = min(lo, sRed[0][w]); hi = max(hi, sRed[1][w]); }
         const bool any = lo <= hi;
         lo = any ? max(lo, 0) : 0;
         hi = any ? min(hi, L.n_cells - 1) : -1;
-        const bool use_lds = any && (hi - lo + 1) <= WMAX;
+        const bool use_lds = any && (hi - lo + 1) <= WW;
         const int span = use_lds ? (hi - lo + 1) : 0;
-        for (int c = threadIdx.x; c < span; c += PUSH_TPB) {
-#pragma unroll
-            for (int r = 0; r < NCOPY; ++r) sJ[r][c] = 0ull;
-            sH[c] = 0;
+        for (int cc = lane; cc < span; cc += 64) {
+            sJ[wid][cc] = 0ull;
+            sH[wid][cc] = 0;
         }
-        __syncthreads();
+        wave_sync();
 
-        // pass 2: advance every particle, deposit into the window (or global memory)
-        Counts cnt;
+        TileCtx T;
+        T.step = step;
+        T.hist_in = hist_in;
+        T.hist_out = hist_out;
+        T.negative = (sp == 0 || sp == 2);
+        T.qm = T.negative ? -1.0f : (sp == 1 ? 1.0f : a.qm_ion);
+        T.inv_mass = (sp == 3) ? a.inv_mass_ion : 1.0f;
+        T.gravity = a.gravity && any && ((double)lo <= L.atm_depth + 1.0 ||
+                                         (double)(L.n_cells - 1 - hi) <= L.atm_depth + 1.0);
         unsigned long long* Jg = a.J + L.cell_base;
-        int* Hg = a.hist_out + 4 * (size_t)L.cell_base + sp;
+        int* Hg = hist_out + 4 * (size_t)L.cell_base + sp;
+
+        CellCache cc;
+        cache_load<GEO>(cc, a, L, first >= 0 ? first : 0);
+        // per-lane run accumulator: deposit and new-cell counts of cells key-1, key, key+1
+        int key = cc.cell;
+        long long jv0 = 0, jv1 = 0, jv2 = 0;
+        int hc0 = 0, hc1 = 0, hc2 = 0;
+        auto flush_run = [&]() {
+            const long long jv[3] = {jv0, jv1, jv2};
+            const int hv[3] = {hc0, hc1, hc2};
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int cell = key - 1 + r;
+                if (cell >= 0 && cell < L.n_cells) {
+                    if (use_lds) {
+                        if (jv[r] != 0) atomicAdd(&sJ[wid][cell - lo], (unsigned long long)jv[r]);
+                        if (hv[r] != 0) atomicAdd(&sH[wid][cell - lo], hv[r]);
+                    } else {
+                        if (jv[r] != 0) atomicAdd(&Jg[cell], (unsigned long long)jv[r]);
+                        if (hv[r] != 0) atomicAdd(&Hg[4 * (size_t)cell], hv[r]);
+                    }
+                }
+            }
+            jv0 = jv1 = jv2 = 0;
+            hc0 = hc1 = hc2 = 0;
+        };
+        // the particle in slot 0 is advanced and its result rotated in at the end, so
+        // the register arrays are only ever indexed by constants
 #pragma unroll 1
         for (int q = 0; q < PUSH_PPT; ++q) {
-            if (cl[q] == DEAD_CELL) continue;
-            const int64_t k = base + i0 + q * PUSH_TPB + threadIdx.x;
-            ++cnt.pushed;
-            int ca, cb, cnew;
+            const int c0 = c[0];
+            const bool alive = c0 != DEAD_CELL;
+            if (alive && c0 != cc.cell) {
+                flush_run();
+                cache_load<GEO>(cc, a, L, c0);
+                key = c0;
+            }
+            float uq = alive ? uu[0] : 0.0f;
+            const float oq = alive ? o[0] : 0.5f;
+            int c1, d;
+            float o1;
             long long da, db;
-            advance_particle<BACKEND>(a, L, line, sp, k, cl[q], cnt, ca, da, cb, db, cnew);
-            if (use_lds) {
-                if (ca >= 0 && ca < L.n_cells && da != 0) atomicAdd(&sJ[copy][ca - lo], (unsigned long long)da);
-                if (cb >= 0 && db != 0) atomicAdd(&sJ[copy][cb - lo], (unsigned long long)db);
-                if (cnew != DEAD_CELL) atomicAdd(&sH[cnew - lo], 1);
-            } else {
-                if (ca >= 0 && ca < L.n_cells && da != 0) atomicAdd(&Jg[ca], (unsigned long long)da);
-                if (cb >= 0 && db != 0) atomicAdd(&Jg[cb], (unsigned long long)db);
-                if (cnew != DEAD_CELL) atomicAdd(&Hg[4 * (size_t)cnew], 1);
+            advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + q, cc.cell, oq, uq, cnt, c1, o1,
+                                      da, db, d);
+            cnt.pushed += alive ? 1 : 0;
+            jv1 += alive ? da : 0ll;
+            jv0 += (alive && d < 0) ? db : 0ll;
+            jv2 += (alive && d > 0) ? db : 0ll;
+            const bool kept = alive && c1 != DEAD_CELL;
+            hc0 += (kept && d < 0) ? 1 : 0;
+            hc1 += (kept && d == 0) ? 1 : 0;
+            hc2 += (kept && d > 0) ? 1 : 0;
+            const int cq = alive ? c1 : DEAD_CELL;
+            const float oo = kept ? o1 : o[0];
+            const float un = alive ? uq : uu[0];
+#pragma unroll
+            for (int r = 0; r < PUSH_PPT - 1; ++r) {
+                c[r] = c[r + 1];
+                o[r] = o[r + 1];
+                uu[r] = uu[r + 1];
+            }
+            c[PUSH_PPT - 1] = cq;
+            o[PUSH_PPT - 1] = oo;
+            uu[PUSH_PPT - 1] = un;
+        }
+        flush_run();
+        // write back (vector stores for full groups; never touch slots >= ncur, where
+        // appended particles may be landing)
+        if (nv == PUSH_PPT) {
+            int4* cp = reinterpret_cast<int4*>(a.cell + base + ib);
+            float4* op = reinterpret_cast<float4*>(a.off + base + ib);
+            float4* up = reinterpret_cast<float4*>(a.u + base + ib);
+#pragma unroll
+            for (int h = 0; h < PUSH_PPT / 4; ++h) {
+                cp[h] = make_int4(c[4 * h], c[4 * h + 1], c[4 * h + 2], c[4 * h + 3]);
+                op[h] = make_float4(o[4 * h], o[4 * h + 1], o[4 * h + 2], o[4 * h + 3]);
+                up[h] = make_float4(uu[4 * h], uu[4 * h + 1], uu[4 * h + 2], uu[4 * h + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < PUSH_PPT; ++q) {
+                if (q < nv) {
+                    a.cell[base + ib + q] = c[q];
+                    a.off[base + ib + q] = o[q];
+                    a.u[base + ib + q] = uu[q];
+                }
             }
         }
-        flush_counts(a, line, cnt);
-        __syncthreads();
         // flush the window
-        for (int c = threadIdx.x; c < span; c += PUSH_TPB) {
-            unsigned long long s = 0;
-#pragma unroll
-            for (int r = 0; r < NCOPY; ++r) s += sJ[r][c];
-            if (s != 0ull) atomicAdd(&Jg[lo + c], s);
-            if (sH[c] != 0) atomicAdd(&Hg[4 * (size_t)(lo + c)], sH[c]);
+        wave_sync();
+        for (int cc2 = lane; cc2 < span; cc2 += 64) {
+            const unsigned long long sj = sJ[wid][cc2];
+            if (sj != 0ull) atomicAdd(&Jg[lo + cc2], sj);
+            const int sh = sH[wid][cc2];
+            if (sh != 0) atomicAdd(&Hg[4 * (size_t)(lo + cc2)], sh);
         }
-        __syncthreads();
+        wave_sync();
     }
+    if (cur_line >= 0) counts_flush(a.counters, cur_line, cnt);
 }
 
 template __global__ void k_push<RICS_OFF>(PushArgs);
 template __global__ void k_push<RICS_EXACT>(PushArgs);
 template __global__ void k_push<RICS_TABLE>(PushArgs);
+
+// ---------------------------------------------------------------------------
+// Photon conversion (Sec. 3): every recorded photon with E >= 2 m_e c^2 turns into
+// an e-/e+ pair at gamma = eps/2 each where it converts -- at the emission point,
+// or where the straight photon leaves the curved line by arcsin(2 m_e c^2/E) --
+// if that point lies on the line and the cell's count at the start of the step
+// is below n_max.  Float64 throughout: the member momenta are ill-conditioned in
+// eps when eps/2 is close to 1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool append_slot(const ConvertArgs& a, int seg, int cell, float off, float u, uint64_t id) {
+    const int slot = atomicAdd(&a.alloc[seg], 1);
+    if (slot >= a.seg_cap[seg]) {
+        set_error(&a.sc->err, -3);
+        return false;
+    }
+    const int64_t k = a.seg_base[seg] + slot;
+    a.cell[k] = cell;
+    a.off[k] = off;
+    a.u[k] = u;
+    a.id[k] = id;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
+    if (a.sc->err != 0) return;
+    const uint64_t step = a.sc->step;
+    const int32_t* hist_in = (step & 1) ? a.hist[1] : a.hist[0];
+    int32_t* hist_out = (step & 1) ? a.hist[0] : a.hist[1];
+    for (int r = blockIdx.x; r < PHOTON_REPL; r += gridDim.x) {
+        const int np = min(a.n_photons[r], a.photon_region);
+        for (int i = threadIdx.x; i < np; i += blockDim.x) {
+            const PhotonRec p = a.photons[(size_t)r * a.photon_region + i];
+            const LineDev& L = a.lines[p.line];
+            const int n = L.n_cells;
+            const double ud = (double)p.u_pre;
+            const double qd = sqrt(1.0 + 2.0 * (double)p.b);
+            const double eps = sqrt(1.0 + ud * ud) * (2.0 * (double)p.b) / (qd * (1.0 + qd));
+            int cs = p.cell;
+            float os = p.off;
+            bool ok = true;
+            if (a.conversion != 0) {
+                const double* rc = a.rc_nodes + L.node_base + p.cell;
+                const double rcx = fma((double)p.off, rc[1] - rc[0], rc[0]);
+                const double sp = (double)p.cell + (double)p.off +
+                                  (double)p.dir * rcx * L.inv_ds * asin(fmin(2.0 / eps, 1.0));
+                ok = (sp >= 0.0) && (sp < (double)n);
+                cs = ok ? (int)floor(sp) : 0;
+                os = ok ? (float)(sp - (double)cs) : 0.0f;
+                if (os >= 1.0f) { os = 0.0f; cs += 1; ok = ok && cs < n; }
+            }
+            bool made = false;
+            if (ok) {
+                const int* hc = hist_in + 4 * (size_t)(L.cell_base + cs);
+                if ((float)(hc[0] + hc[1] + hc[2] + hc[3]) < L.nmax) {
+                    const double gp = 0.5 * eps;
+                    const float up = p.dir * (float)sqrt(fmax((gp - 1.0) * (gp + 1.0), 0.0));
+                    const uint4 wc = philox4x32_10(make_uint4((uint32_t)step, (uint32_t)p.pid,
+                                                              (uint32_t)(p.pid >> 32), STREAM_CHILD), a.key0, a.key1);
+                    const bool e_ok = append_slot(a, 4 * p.line + 0, cs, os, up, id_from_words(wc.x, wc.y));
+                    const bool p_ok = append_slot(a, 4 * p.line + 1, cs, os, up, id_from_words(wc.z, wc.w));
+                    if (e_ok && p_ok) {
+                        int* ho = hist_out + 4 * (size_t)(L.cell_base + cs);
+                        atomicAdd(&ho[0], 1);
+                        atomicAdd(&ho[1], 1);
+                        atomicAdd(&a.pair_step[L.cell_base + cs], 1);
+                        made = true;
+                    }
+                }
+            }
+            const size_t rep = ((size_t)p.line * CNT_REPL + (i & (CNT_REPL - 1))) * NCOUNT;
+            atomicAdd(&a.counters[rep + (made ? 1 : 2)], 1ull);
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Atmosphere (Appendix B.1): every layer cell is refilled to its hydrostatic
@@ -447,7 +692,8 @@ __global__ __launch_bounds__(256) void k_atmosphere(AtmArgs a) {
         if (lane == 0) {
             h[2] += D;
             h[3] += D;
-            atomicAdd(&a.counters[line * NCOUNT + 7], (unsigned long long)D);
+            atomicAdd(&a.counters[((size_t)line * CNT_REPL + (blockIdx.x & (CNT_REPL - 1))) * NCOUNT + 7],
+                      (unsigned long long)D);
         }
     }
 }
@@ -458,6 +704,7 @@ __global__ __launch_bounds__(256) void k_atmosphere(AtmArgs a) {
 // ---------------------------------------------------------------------------
 __device__ void bookkeeping(const BookArgs& b) {
     if (b.sc->err != 0) return;
+    if (b.n_photons && threadIdx.x < PHOTON_REPL) b.n_photons[threadIdx.x] = 0;
     __shared__ int sPart[256];
     const int nseg = b.nseg;
     const int per = (nseg + 255) / 256;
@@ -572,7 +819,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs s) {
         const int cap = s.seg_cap[seg];
         const int64_t base = s.seg_base[seg];
         const int i0 = (t - s.tile_prefix[seg]) * PUSH_TILE;
-        for (int q = 0; q < PUSH_PPT; ++q) {
+        for (int q = 0; q < AUX_PPT; ++q) {
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
             const int c = (i < ncur) ? s.cell[base + i] : DEAD_CELL;
             bool pending = (c != DEAD_CELL);
@@ -648,7 +895,7 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs h) {
         const int ncur = h.n_cur[seg];
         const int64_t base = h.seg_base[seg];
         const int i0 = (t - h.tile_prefix[seg]) * PUSH_TILE;
-        for (int q = 0; q < PUSH_PPT; ++q) {
+        for (int q = 0; q < AUX_PPT; ++q) {
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
             if (i >= ncur) continue;
             const int c = h.cell[base + i];
@@ -675,15 +922,17 @@ __global__ __launch_bounds__(256) void k_moments_particles(MomArgs m) {
         const int i0 = (t - m.tile_prefix[seg]) * PUSH_TILE;
         const double qs = m.sign[sp] * FIX_SCALE;
         const double mass = (sp == 3) ? m.mass_ratio : 1.0;
-        for (int q = 0; q < PUSH_PPT; ++q) {
+        for (int q = 0; q < AUX_PPT; ++q) {
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
             if (i >= ncur) continue;
             const int c = m.cell[base + i];
             if (c == DEAD_CELL) continue;
-            const double o = (double)m.off[base + i];
+            // cloud-in-cell weights of the position quantised to 2^-32 cell, as in the deposit
+            const long long f = (long long)__float2uint_rn(m.off[base + i] * 4294967296.0f);
+            const long long sg = (qs < 0.0) ? -1 : 1;
             const double u = (double)m.u[base + i];
-            atomicAdd(&m.rho[c], (unsigned long long)__double2ll_rn((1.0 - o) * qs));
-            atomicAdd(&m.rho[c + 1], (unsigned long long)__double2ll_rn(o * qs));
+            atomicAdd(&m.rho[c], (unsigned long long)(sg * (4294967296ll - f)));
+            atomicAdd(&m.rho[c + 1], (unsigned long long)(sg * f));
             kin += mass * L.Q * (double)L.C * (double)L.C * (sqrt(1.0 + u * u) - 1.0);
         }
     }
@@ -729,16 +978,20 @@ __global__ __launch_bounds__(256) void k_rics_eval(PushArgs a, int line, int64_t
     if (i >= n) return;
     const LineDev L = a.lines[line];
     const float s = fminf(fmaxf(s_cells[i], 0.0f), (float)L.n_cells);
-    int c0 = min((int)floorf(s), L.n_cells - 1);
+    const int c0 = min((int)floorf(s), L.n_cells - 1);
     const float o0 = s - (float)c0;
-    const Geo g = geo_at(a.nodes, L.node_base + c0, o0);
+    const double x = (double)c0 + (double)o0;
+    const PartGeo pg = part_geo<BACKEND>(L, a.nodes[L.node_base + c0], a.nodes[L.node_base + c0 + 1], o0, x, a.ns);
+    const Geo& g = pg.g;
     const float u = uin[i];
-    RicsOut r;
-    if constexpr (BACKEND == RICS_OFF) { r.F = 0.0f; r.dF = 0.0f; r.N = 0.0f; }
-    else r = rics_eval<BACKEND>(a, L, u, g, c0, o0);
-    F[i] = r.F;
-    N[i] = r.N;
-    eps[i] = photon_energy(sqrtf(fmaf(u, u, 1.0f)), g.b);
+    float f = 0.0f, nd = 0.0f, unused;
+    if constexpr (BACKEND != RICS_OFF) {
+        f = rics_F<BACKEND, false>(a, L, u, pg, unused);
+        nd = rics_N<BACKEND>(a, L, u, pg);
+    }
+    F[i] = f;
+    N[i] = nd;
+    eps[i] = photon_energy(fsqrt(fmaf(u, u, 1.0f)), g.b);
 }
 template __global__ void k_rics_eval<RICS_OFF>(PushArgs, int, int64_t, const float*, const float*, float*, float*, float*);
 template __global__ void k_rics_eval<RICS_EXACT>(PushArgs, int, int64_t, const float*, const float*, float*, float*, float*);

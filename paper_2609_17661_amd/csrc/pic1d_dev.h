@@ -36,7 +36,7 @@ struct LineDev {
     int32_t cell_base;    // first global cell
     int32_t n_cells;
     int32_t node_base;    // first global node = cell_base + line index
-    int32_t table_off;    // float offset of the F table of this line (N table follows)
+    int32_t table_off;    // float4 offset of this line's RICS table
     float C, invC;        // cells per step at c, and its inverse
     float h;              // one step in R*/c
     float tau_hat;        // tau_min in R*/c
@@ -47,6 +47,9 @@ struct LineDev {
     float grav;           // T C / h_atm: |du| per step of a unit-mass particle in the layer
     float nmax;           // n_max per cell (all species)
     float half_n;         // n_cells / 2
+    float lgk;            // table: (nlg - 1)/8 log10(2): fractional column per unit log2 gamma
+    float lgk_hi, lgk_lo; // lgk split into a 10-fraction-bit head and the rest
+    float pad1;
     double s_scale;       // table: ns / n_cells
     double lg_scale;      // table: (nlg - 1) / 8
     double atm_depth;     // gravity layer depth (cells from each wall)

@@ -138,6 +138,13 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
     d.b_thr = (float)c->b_thr;
     d.s_scale = c->rics_backend == 2 ? (double)c->table_ns / n : 0.0;
     d.lg_scale = c->rics_backend == 2 ? (c->table_nlg - 1) / 8.0 : 0.0;
+    {
+        const double k = d.lg_scale * log10(2.0);
+        const double k_hi = floor(k * 1024.0) / 1024.0;
+        d.lgk = (float)k;
+        d.lgk_hi = (float)k_hi;
+        d.lgk_lo = (float)(k - k_hi);
+    }
     const double nmax = (c->nmax_over_n0 > 0.0 ? c->nmax_over_n0 : c->d0_cells * c->d0_cells) * c->ppc0;
     d.nmax = (float)nmax;
     d.half_n = 0.5f * (float)n;
@@ -184,21 +191,28 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
         o.rc[i] = g.rc;
     }
 
-    // RICS table for u >= 0 at log10 gamma_i = 8 i/(nlg-1), s_j = (j + 1/2) L/ns
+    // RICS table for u >= 0 at log10 gamma_i = 8 i/(nlg-1), s_j = (j + 1/2) L/ns, stored as
+    // [ns][nlg] records {F(i), F(i+1), Ndot(i), Ndot(i+1)} (column i+1 clamped at the end)
     o.table.clear();
     if (c->rics_backend == 2) {
         const int nlg = c->table_nlg, ns = c->table_ns;
-        o.table.assign(2 * (size_t)nlg * ns, 0.0f);
+        std::vector<double> Fr(nlg), Nr(nlg);
+        o.table.assign(4 * (size_t)nlg * ns, 0.0f);
         for (int j = 0; j < ns; ++j) {
             const double s = (j + 0.5) * o.L_rstar / ns;
             const NodeGeo g = geometry_at(R, c->b_pole, cos_theta_at(R, s));
             for (int i = 0; i < nlg; ++i) {
                 const double gam = pow(10.0, 8.0 * i / (nlg - 1));
                 const double u = sqrt(fmax(gam * gam - 1.0, 0.0));
-                double F, N;
-                rics_closed(u, g.b, g.mu, g.x, theta, AF, AN, F, N);
-                o.table[(size_t)j * nlg + i] = (float)F;
-                o.table[(size_t)nlg * ns + (size_t)j * nlg + i] = (float)N;
+                rics_closed(u, g.b, g.mu, g.x, theta, AF, AN, Fr[i], Nr[i]);
+            }
+            for (int i = 0; i < nlg; ++i) {
+                const int i1 = std::min(i + 1, nlg - 1);
+                float* rec = &o.table[4 * ((size_t)j * nlg + i)];
+                rec[0] = (float)Fr[i];
+                rec[1] = (float)Fr[i1];
+                rec[2] = (float)Nr[i];
+                rec[3] = (float)Nr[i1];
             }
         }
     }
@@ -210,7 +224,8 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
     defcap[2] = defcap[3] = c->atmosphere ? 4 * atm_total + 4096 : 64;
     for (int s = 0; s < 4; ++s) {
         o.cap[s] = ln.capacity[s] > 0 ? ln.capacity[s] : defcap[s];
-        o.cap[s] = std::min<int64_t>(o.cap[s], (1ll << 31) - 1);
+        // multiples of 256 slots keep every segment aligned for vector loads
+        o.cap[s] = std::min<int64_t>((o.cap[s] + 255) / 256 * 256, (1ll << 31) - 256);
     }
 }
 
