@@ -48,7 +48,7 @@ import math
 
 import numpy as np
 
-from . import drag, geometry, philox, rics
+from . import drag, geometry, mlp, philox, rics
 
 N_SPECIES = 4
 SPECIES_SIGN = (-1.0, +1.0, -1.0, +1.0)
@@ -64,7 +64,7 @@ DEFAULTS = dict(
     eta_min=1.0e3, b_thr=0.1, mass_ratio=100.0, rics="table", table_nlg=256,
     table_ns=512, pairs=False, conversion="immediate", nmax_over_n0=0.0,
     atmosphere=False, atm_a0=0.0, atm_h_cells=0.0, atm_T=0.01, atm_cut=0.01,
-    gravity=True, frozen_field=False, seed=0, lines=None,
+    gravity=True, frozen_field=False, seed=0, lines=None, mlp_params=None, mlp_norm=None,
 )
 
 
@@ -135,6 +135,18 @@ class Line:
         if mode == 'off':
             z = lambda u: np.zeros_like(np.asarray(u, dtype=np.float64))
             return z, z, z
+        if mode == 'mlp':
+            # the surrogate network (oracle/mlp.py), fed the arc-length fraction of the
+            # particle (u >= 0) or of its mirror point (u < 0)
+            P, norm = cfg['mlp_params'], cfg['mlp_norm']
+            sl = xc / self.n
+
+            def args(u):
+                u = np.asarray(u, dtype=np.float64)
+                return u, np.where(u >= 0, sl, 1.0 - sl), b, mu, xr, kT
+            return (lambda u: mlp.surrogate_rics(P, norm, *args(u))[0],
+                    lambda u: mlp.surrogate_force_du(P, norm, *args(u)),
+                    lambda u: mlp.surrogate_rics(P, norm, *args(u))[1])
         raise ValueError(f"unknown rics mode {mode!r}")
 
 
