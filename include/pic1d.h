@@ -130,7 +130,8 @@ typedef struct {
     uint64_t seed;            /* Philox key                                  */
     int32_t sort_interval;    /* steps between cell sorts; 0 = never         */
     int32_t avg_start_step;   /* accumulate averages from this step; < 0 off */
-    const void* mlp_weights;  /* MLP backend: host, packed fp32 weights (pic1d_mlp_param_count floats) */
+    const float* mlp_weights; /* MLP backend: host, pic1d_mlp_param_count() fp32 parameters */
+    const float* mlp_norm;    /* MLP backend: host, 6 floats: output mean[3], std[3] */
     void* workspace;          /* device, >= pic1d_workspace_size bytes, 256-B aligned */
     size_t workspace_bytes;
     void* stream;             /* hipStream_t all work is enqueued on          */
@@ -229,6 +230,87 @@ int pic1d_profile_read(pic1d_state* st, pic1d_profile_out* out);
  * Errors: EINVAL. */
 int pic1d_rics_eval(pic1d_state* st, int32_t line, int64_t n, const float* s_cells,
                     const float* u, float* F, float* ndot, float* eps);
+
+/* ---------------------------------------------------------------------------
+ * RICS surrogate network (RICS backend PIC1D_RICS_MLP).
+ *
+ * The paper evaluates the RICS drag force and scattering rate from their
+ * definitions (Sec. 2.2, Eqs. scatteringNdot and contdrag) and proposes no
+ * surrogate; this network is an addition trained on those definitions.
+ * Inputs (log10 gamma, s/L, log10(B/B_QED), kT/keV) on [0,8] x [0,1] x [-2,3] x
+ * [0.3,1], s/L along the R_max = 4 dipole line (Appendix B.2); network
+ * 4 -> 128 -> 128 -> 128 -> 128 -> 3 with SiLU; outputs the normalised targets
+ * (o_k - mean_k)/std_k of o1 = log10(|F_hat|/|gamma mu - u|), o2 = log10(Ndot_hat),
+ * o3 = log10(eps) (Appendix A.3) for u >= 0; negative u by the mirror
+ * F(-u, s) = -F(u, L - s).  Weights run on the matrix cores in bfloat16 with
+ * float32 accumulation (activations as three bfloat16 terms).
+ *
+ * Parameters: PIC1D_MLP_NPARAM floats, [W1 (128x4, row-major), b1, W2 (128x128),
+ * b2, W3, b3, W4, b4, W5 (3x128), b5].  Inputs x: n x 4 floats (raw, not
+ * normalised); targets o: n x 4 floats (o1, o2, o3, 0).  Device pointers must be
+ * 16-byte aligned; workspaces 256-byte aligned.  Stateless calls report errors
+ * through pic1d_last_error(NULL).
+ * ------------------------------------------------------------------------- */
+#define PIC1D_MLP_NPARAM 50563
+
+int pic1d_mlp_param_count(void);
+
+/* Device workspace for a batch of `batch` samples and a training pool of
+ * n_pool samples (0 for forward / loss_grad only). */
+int pic1d_mlp_workspace_size(int64_t batch, int64_t n_pool, size_t* bytes);
+
+/* Samples first .. first+n-1 of the seeded sample stream: sample i takes the
+ * first Philox block (counter (i_lo, i_hi, attempt, 7), key = seed) whose
+ * inputs log10 gamma = 8 U0, s/L = U1, log10 b = -2 + 5 U2, kT = 0.3 + 0.7 U3
+ * lie within the Planck cutoff y <= 80; targets in float64, stored float32.
+ * x, o: device, n x 4 floats.  Synchronises the stream.  Errors: EINVAL. */
+int pic1d_mlp_samples(uint64_t seed, int64_t first, int64_t n, float* x, float* o, void* stream);
+
+/* Network outputs (normalised targets, n x 3 floats, device) for raw inputs x
+ * (device, n x 4) with parameters `params` (device, fp32).  Synchronises.
+ * Errors: EINVAL, ENOMEM (workspace), EDEVICE. */
+int pic1d_mlp_forward(const float* params, int64_t n, const float* x, float* out, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* Mean squared error of the network outputs against normalised targets t
+ * (device, n x 3) and its gradient with respect to the bfloat16-rounded weights
+ * and the biases (grad: device, PIC1D_MLP_NPARAM floats); *loss (host) may be
+ * NULL.  Synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int pic1d_mlp_loss_grad(const float* params, int64_t n, const float* x, const float* t, float* grad,
+                        double* loss, void* workspace, size_t workspace_bytes, void* stream);
+
+/* One Adam step (Kingma & Ba 2015, Algorithm 1) on device arrays of
+ * PIC1D_MLP_NPARAM floats; t >= 1 is the step number.  Synchronises. */
+int pic1d_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t t, double lr, double beta1,
+                   double beta2, double eps, void* stream);
+
+typedef struct {
+    uint64_t seed;            /* sample stream, initial weights and batches */
+    int64_t n_samples;        /* training pool: samples 0 .. n_samples-1 of the stream */
+    int32_t batch;            /* samples per Adam step, drawn with replacement */
+    int32_t steps;            /* Adam steps                                   */
+    double lr, lr_final;      /* cosine schedule from lr to lr_final          */
+    double beta1, beta2, eps; /* Adam constants; <= 0 selects 0.9, 0.999, 1e-8 */
+    const float* init_params; /* host initial parameters, or NULL for Glorot-uniform weights from seed */
+    void* workspace;          /* device, >= pic1d_mlp_workspace_size(batch, n_samples) */
+    size_t workspace_bytes;
+    void* stream;
+} pic1d_mlp_train_config;
+
+typedef struct {
+    float* params;            /* host out: PIC1D_MLP_NPARAM floats            */
+    float* norm;              /* host out: mean[3], std[3] of the targets      */
+    double* loss;             /* host out (optional): loss at n_loss evenly spaced steps */
+    int32_t n_loss;           /* in: capacity of loss; out: entries written   */
+    double loss_first, loss_last;
+    double seconds;           /* wall time of the call                        */
+} pic1d_mlp_train_result;
+
+/* Train the network on the GPU: draw the sample pool, normalise the targets by
+ * their mean and standard deviation, then `steps` Adam steps on batches drawn
+ * from the pool, each a forward, backward and weight-gradient pass on the
+ * matrix cores.  Errors: EINVAL, ENOMEM, EDEVICE, ENONFINITE. */
+int pic1d_mlp_train(const pic1d_mlp_train_config* cfg, pic1d_mlp_train_result* res);
 
 #ifdef __cplusplus
 }

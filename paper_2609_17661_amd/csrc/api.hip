@@ -98,6 +98,15 @@ int fail(pic1d_state* st, int code, const std::string& msg) {
     return code;
 }
 
+}  // namespace
+
+namespace pic1d {
+// error of a call without a state handle (pic1d_last_error(NULL))
+int set_global_error(int code, const std::string& msg) { return fail(nullptr, code, msg); }
+}  // namespace pic1d
+
+namespace {
+
 // Synchronous copy ordered on the state's stream.
 hipError_t copy_sync(hipStream_t s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
     hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);

@@ -42,7 +42,7 @@ class CConfig(ctypes.Structure):
                 ("nmax_over_n0", ctypes.c_double), ("atm_a0", ctypes.c_double), ("atm_h_cells", ctypes.c_double),
                 ("atm_T", ctypes.c_double), ("atm_cut", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("sort_interval", ctypes.c_int32), ("avg_start_step", ctypes.c_int32),
-                ("mlp_weights", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("mlp_weights", ctypes.c_void_p), ("mlp_norm", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
 
 
@@ -65,6 +65,20 @@ class CProfile(ctypes.Structure):
 
 KERNELS = ("push", "atmosphere", "field", "plan", "sort", "convert")
 
+
+class CMlpTrainConfig(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_samples", ctypes.c_int64), ("batch", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("lr", ctypes.c_double), ("lr_final", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("init_params", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+
+
+class CMlpTrainResult(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("norm", ctypes.c_void_p), ("loss", ctypes.c_void_p),
+                ("n_loss", ctypes.c_int32), ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
 P = ctypes.c_void_p
 _SIGS = {
     "pic1d_workspace_size": (ctypes.c_int, [ctypes.POINTER(CConfig), ctypes.POINTER(ctypes.c_size_t)]),
@@ -82,6 +96,15 @@ _SIGS = {
     "pic1d_rics_eval": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int64, P, P, P, P, P]),
     "pic1d_profile": (ctypes.c_int, [P, ctypes.c_int32]),
     "pic1d_profile_read": (ctypes.c_int, [P, ctypes.POINTER(CProfile)]),
+    "pic1d_mlp_param_count": (ctypes.c_int, []),
+    "pic1d_mlp_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "pic1d_mlp_samples": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, P, P, P]),
+    "pic1d_mlp_forward": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]),
+    "pic1d_mlp_loss_grad": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_double), P,
+                                           ctypes.c_size_t, P]),
+    "pic1d_mlp_adam": (ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, P]),
+    "pic1d_mlp_train": (ctypes.c_int, [ctypes.POINTER(CMlpTrainConfig), ctypes.POINTER(CMlpTrainResult)]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -157,7 +180,7 @@ def workspace_size(cfg):
 class Pic1D:
     """One simulation state on the current HIP device (all lines of a config)."""
 
-    def __init__(self, cfg, device="cuda", mlp_weights=None):
+    def __init__(self, cfg, device="cuda", mlp_weights=None, mlp_norm=None):
         import torch
 
         self._torch = torch
@@ -176,6 +199,9 @@ class Pic1D:
         if mlp_weights is not None:
             self._mlp = np.ascontiguousarray(mlp_weights, dtype=np.float32)
             c.mlp_weights = ctypes.c_void_p(self._mlp.ctypes.data)
+        if mlp_norm is not None:
+            self._mlp_norm = np.ascontiguousarray(mlp_norm, dtype=np.float32).reshape(6)
+            c.mlp_norm = ctypes.c_void_p(self._mlp_norm.ctypes.data)
         h = ctypes.c_void_p()
         rc = self.lib.pic1d_init(ctypes.byref(c), ctypes.byref(h))
         if rc != 0:
@@ -278,3 +304,104 @@ class Pic1D:
                                              ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(F.data_ptr()),
                                              ctypes.c_void_p(N.data_ptr()), ctypes.c_void_p(eps.data_ptr())))
         return F, N, eps
+
+
+# ---------------------------------------------------------------------------
+# RICS surrogate network (pic1d_mlp_*): device tensors are torch float32
+# ---------------------------------------------------------------------------
+
+def _raise_global(rc):
+    if rc != 0:
+        raise Pic1dError(rc, load().pic1d_last_error(None).decode())
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def mlp_param_count():
+    return load().pic1d_mlp_param_count()
+
+
+def _mlp_workspace(batch, n_pool, device):
+    import torch
+    n = ctypes.c_size_t(0)
+    _raise_global(load().pic1d_mlp_workspace_size(int(batch), int(n_pool), ctypes.byref(n)))
+    return torch.empty(n.value, dtype=torch.uint8, device=device)
+
+
+def mlp_samples(seed, first, n, device="cuda"):
+    """Inputs (n x 4) and float32 targets (n x 4: o1, o2, o3, 0) of the seeded sample stream."""
+    import torch
+    x = torch.empty((max(n, 1), 4), dtype=torch.float32, device=device)
+    o = torch.empty((max(n, 1), 4), dtype=torch.float32, device=device)
+    _raise_global(load().pic1d_mlp_samples(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first), int(n), _dev_ptr(x),
+                                           _dev_ptr(o), _stream(x.device)))
+    return x[:n], o[:n]
+
+
+def mlp_forward(params, x):
+    """Network outputs (normalised targets, n x 3) for raw inputs x (n x 4); params: float32 device tensor."""
+    import torch
+    n = x.shape[0]
+    out = torch.empty((max(n, 1), 3), dtype=torch.float32, device=x.device)
+    ws = _mlp_workspace(1, 0, x.device)
+    _raise_global(load().pic1d_mlp_forward(_dev_ptr(params.contiguous()), n, _dev_ptr(x.contiguous()), _dev_ptr(out),
+                                           _dev_ptr(ws), ws.numel(), _stream(x.device)))
+    return out[:n]
+
+
+def mlp_loss_grad(params, x, t):
+    """(loss, gradient) of the mean squared error against normalised targets t (n x 3)."""
+    import torch
+    n = x.shape[0]
+    grad = torch.empty(mlp_param_count(), dtype=torch.float32, device=x.device)
+    ws = _mlp_workspace(n, 0, x.device)
+    loss = ctypes.c_double(0.0)
+    _raise_global(load().pic1d_mlp_loss_grad(_dev_ptr(params.contiguous()), n, _dev_ptr(x.contiguous()),
+                                             _dev_ptr(t.contiguous()), _dev_ptr(grad), ctypes.byref(loss),
+                                             _dev_ptr(ws), ws.numel(), _stream(x.device)))
+    return loss.value, grad
+
+
+def mlp_adam(params, m, v, grad, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place on float32 device tensors."""
+    _raise_global(load().pic1d_mlp_adam(_dev_ptr(params), _dev_ptr(m), _dev_ptr(v), _dev_ptr(grad), int(t),
+                                        float(lr), float(beta1), float(beta2), float(eps), _stream(params.device)))
+
+
+def mlp_train(seed=0, n_samples=1 << 22, batch=8192, steps=20000, lr=2e-3, lr_final=1e-5, init_params=None,
+              n_loss=50, device="cuda"):
+    """Train the surrogate on the GPU; returns dict(params, norm, loss, loss_first, loss_last, seconds)."""
+    ws = _mlp_workspace(batch, n_samples, device)
+    c = CMlpTrainConfig()
+    c.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    c.n_samples = int(n_samples)
+    c.batch = int(batch)
+    c.steps = int(steps)
+    c.lr = float(lr)
+    c.lr_final = float(lr_final)
+    keep = None
+    if init_params is not None:
+        keep = np.ascontiguousarray(init_params, dtype=np.float32)
+        c.init_params = ctypes.c_void_p(keep.ctypes.data)
+    c.workspace = _dev_ptr(ws)
+    c.workspace_bytes = ws.numel()
+    c.stream = _stream(ws.device)
+    params = np.zeros(mlp_param_count(), dtype=np.float32)
+    norm = np.zeros(6, dtype=np.float32)
+    loss = np.zeros(max(n_loss, 1), dtype=np.float64)
+    r = CMlpTrainResult()
+    r.params = ctypes.c_void_p(params.ctypes.data)
+    r.norm = ctypes.c_void_p(norm.ctypes.data)
+    r.loss = ctypes.c_void_p(loss.ctypes.data)
+    r.n_loss = int(n_loss)
+    _raise_global(load().pic1d_mlp_train(ctypes.byref(c), ctypes.byref(r)))
+    del keep
+    return dict(params=params, norm=norm, loss=loss[:r.n_loss].copy(), loss_first=r.loss_first,
+                loss_last=r.loss_last, seconds=r.seconds)

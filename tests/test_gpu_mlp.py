@@ -1,0 +1,128 @@
+"""Parity of the surrogate-network kernels (bfloat16 MFMA) with the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_2609_17661_amd import pic1d
+
+pytestmark = pytest.mark.gpu
+
+# The forward pass carries activations as three bfloat16 terms (24 significant
+# bits) with float32 accumulation over at most 128 products per layer, so the
+# outputs agree with the float64 evaluation of the same bfloat16 weights to a
+# few float32 ulps of the accumulated magnitudes: OUT_TOL absolute on outputs of
+# order one.  Gradients: GRAD_TOL relative in the 2-norm of each layer's block.
+OUT_TOL = 2e-6
+GRAD_TOL = 2e-6
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for o, i in omlp.LAYERS:
+        parts.append((rng.uniform(-1, 1, (o, i)) * scale * omlp.glorot_bound(o, i), rng.uniform(-0.2, 0.2, o)))
+    return omlp.pack(parts)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _box_inputs(seed, n):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(0, 8, n), rng.uniform(0, 1, n), rng.uniform(-2, 3, n),
+                     rng.uniform(0.3, 1, n)], axis=1).astype(np.float32)
+
+
+def test_sample_stream_matches_oracle():
+    torch = _torch()
+    first, n = 123456789012, 4001
+    _print("mlp samples", first, n)
+    x, o = pic1d.mlp_samples(11, first, n)
+    X, O, used = omlp.training_samples(seed=11, n=n, first=first)
+    xg = x.cpu().numpy()
+    og = o.cpu().numpy().astype(np.float64)
+    assert np.array_equal(xg, X), "inputs are 24-bit uniforms mapped in float64 and stored float32: bit-exact"
+    # targets: float64 on both sides, stored float32 on the GPU (half an ulp of |o| <= 32)
+    err = np.abs(og[:, :3] - O)
+    assert np.all(err <= 2.0 ** -24 * np.maximum(np.abs(O), 1.0) + 1e-9), err.max()
+    assert np.all(og[:, 3] == 0.0)
+    _print("attempts used up to", used.max(), "max target error", err.max())
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [1, 16, 1001])
+def test_forward_matches_oracle(n):
+    torch = _torch()
+    p = _params(21, 1.5)
+    X = _box_inputs(22, n)
+    _print("mlp forward n", n)
+    out = pic1d.mlp_forward(torch.from_numpy(p.astype(np.float32)).cuda(), torch.from_numpy(X).cuda())
+    ref, _ = omlp.forward(p.astype(np.float32).astype(np.float64), omlp.normalize_inputs(X.astype(np.float64)))
+    got = out.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref)
+    _print("max |out - oracle|", err.max(), "max |out|", np.abs(ref).max())
+    assert np.all(err <= OUT_TOL * np.maximum(1.0, np.abs(ref)))
+
+
+def test_loss_and_gradient_match_oracle():
+    torch = _torch()
+    n = 777          # ragged against the 16-sample groups and the 256-sample gradient chunks
+    p = _params(31, 1.5).astype(np.float32).astype(np.float64)
+    X = _box_inputs(32, n)
+    T = np.random.default_rng(33).standard_normal((n, 3)).astype(np.float32)
+    _print("mlp loss_grad n", n)
+    loss, g = pic1d.mlp_loss_grad(torch.from_numpy(p.astype(np.float32)).cuda(), torch.from_numpy(X).cuda(),
+                                  torch.from_numpy(T).cuda())
+    L, gref = omlp.loss_and_grad(p, omlp.normalize_inputs(X.astype(np.float64)), T.astype(np.float64))
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss - L) <= 1e-5 * L
+    k = 0
+    for o, i in omlp.LAYERS:
+        for size in (o * i, o):
+            a, b = g[k:k + size], gref[k:k + size]
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            _print("block", o, i, size, "relative error", rel)
+            assert rel <= GRAD_TOL
+            k += size
+
+
+def test_adam_step_matches_oracle():
+    torch = _torch()
+    rng = np.random.default_rng(41)
+    n = omlp.N_PARAM
+    th = rng.standard_normal(n).astype(np.float32)
+    m = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    v = (rng.uniform(0, 1e-3, n)).astype(np.float32)
+    g = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    t, lr = 5, 1e-3
+    dt = [torch.from_numpy(a.copy()).cuda() for a in (th, m, v, g)]
+    pic1d.mlp_adam(dt[0], dt[1], dt[2], dt[3], t, lr)
+    ref, mref, vref = omlp.adam_step(th.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                                     g.astype(np.float64), t, lr)
+    # the new parameter is rounded to float32: one ulp of theta plus float32 arithmetic on the step
+    got = dt[0].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -23 * np.abs(ref) + 1e-5 * np.abs(ref - th))
+    # moments: float32 rounding of the constants and of the two terms of each update (they may cancel)
+    mb = 2.0 ** -21 * (0.9 * np.abs(m) + 0.1 * np.abs(g))
+    vb = 2.0 ** -21 * (0.999 * v + 0.001 * g.astype(np.float64) ** 2)
+    assert np.all(np.abs(dt[1].cpu().numpy() - mref) <= mb)
+    assert np.all(np.abs(dt[2].cpu().numpy() - vref) <= vb)
+
+
+def test_training_on_the_gpu_reduces_the_loss():
+    _print("mlp train small")
+    r = pic1d.mlp_train(seed=5, n_samples=1 << 16, batch=2048, steps=300, lr=2e-3, lr_final=1e-4, n_loss=10)
+    _print("loss", r["loss_first"], "->", r["loss_last"], "in", r["seconds"], "s")
+    assert np.all(np.isfinite(r["params"]))
+    assert r["loss_last"] < 0.05 * r["loss_first"]
+    # the normalisation is the mean and standard deviation of the pool's targets (oracle, float64)
+    X, O, _ = omlp.training_samples(seed=5, n=1 << 16)
+    mean, std = omlp.normalisation(O)
+    assert np.allclose(r["norm"][:3], mean, rtol=1e-5, atol=1e-5)
+    assert np.allclose(r["norm"][3:], std, rtol=1e-5)
