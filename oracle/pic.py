@@ -138,7 +138,9 @@ class Line:
         if mode == 'mlp':
             # the surrogate network (oracle/mlp.py), fed the arc-length fraction of the
             # particle (u >= 0) or of its mirror point (u < 0)
-            P, norm = cfg['mlp_params'], cfg['mlp_norm']
+            P = np.asarray(cfg['mlp_params'], dtype=np.float64)
+            nm = np.asarray(cfg['mlp_norm'], dtype=np.float64).reshape(2, 3)
+            norm = (nm[0], nm[1])
             sl = xc / self.n
 
             def args(u):

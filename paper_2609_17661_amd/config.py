@@ -38,6 +38,8 @@ DEFAULTS = dict(
     sort_interval=0,
     avg_start_step=-1,
     lines=None,
+    mlp_params=None,    # RICS "mlp": the network's 50,563 parameters (float32 values)
+    mlp_norm=None,      # RICS "mlp": output mean[3] and std[3]
 )
 
 

@@ -40,6 +40,7 @@ struct Layout {
     int64_t table_floats = 0;
     int32_t n_layer = 0;
     int32_t photon_region = 0;   // photon records per append region
+    bool mlp = false;            // surrogate-network RICS backend
 };
 
 }  // namespace
@@ -80,6 +81,11 @@ struct pic1d_state {
     double* mom_out = nullptr;
     PhotonRec* photons = nullptr;
     int32_t* n_photons = nullptr;
+    float* mlp_params = nullptr;
+    bf16x8* mlp_ft = nullptr;
+    bf16x8* mlp_bt = nullptr;
+    float* mlp_bias = nullptr;
+    float mlp_norm[6] = {0, 0, 0, 1, 1, 1};
     // per-kernel event timing (pic1d_profile)
     int prof_on = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -145,6 +151,7 @@ Layout plan_layout(const pic1d_config* c, std::vector<LineHost>* lines_out) {
     L.photon_region = (int32_t)std::min<int64_t>(std::max<int64_t>(256, (L.total_slots / 4 + PHOTON_REPL - 1) / PHOTON_REPL),
                                                  (1ll << 30) / PHOTON_REPL);
     L.table_floats = toff;
+    L.mlp = c->rics_backend == PIC1D_RICS_MLP;
     return L;
 }
 
@@ -191,6 +198,10 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->mom_out = cv.take<double>(8);
     s->photons = cv.take<PhotonRec>(c_pairs(L) ? (size_t)PHOTON_REPL * L.photon_region : 1);
     s->n_photons = cv.take<int32_t>(PHOTON_REPL);
+    s->mlp_params = cv.take<float>(L.mlp ? MLP_NPARAM : 1);
+    s->mlp_ft = cv.take<bf16x8>(L.mlp ? FT_TOTAL * 64 : 1);
+    s->mlp_bt = cv.take<bf16x8>(L.mlp ? BT_TOTAL * 64 : 1);
+    s->mlp_bias = cv.take<float>(L.mlp ? MLP_BIAS : 1);
 }
 
 PushArgs push_args(pic1d_state* st) {
@@ -206,6 +217,9 @@ PushArgs push_args(pic1d_state* st) {
     a.table = st->table; a.hist[0] = st->hist[0]; a.hist[1] = st->hist[1];
     a.pair_step = st->pair_step; a.counters = st->counters; a.sc = st->sc;
     a.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); a.key1 = (uint32_t)(st->cfg.seed >> 32);
+    a.mlp_ft = st->mlp_ft; a.mlp_bias = st->mlp_bias;
+    for (int k = 0; k < 3; ++k) { a.mlp_mean[k] = st->mlp_norm[k]; a.mlp_std[k] = st->mlp_norm[3 + k]; }
+    a.mlp_kTn = (float)((st->cfg.kT_keV - 0.3) * (2.0 / 0.7) - 1.0);
     a.qm_ion = (float)(1.0 / st->cfg.mass_ratio);
     a.inv_mass_ion = (float)(1.0 / st->cfg.mass_ratio);
     a.photons = st->photons;
@@ -259,6 +273,7 @@ int launch_push(pic1d_state* st) {
         case RICS_OFF: hipLaunchKernelGGL(k_push<RICS_OFF>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
         case RICS_EXACT: hipLaunchKernelGGL(k_push<RICS_EXACT>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
         case RICS_TABLE: hipLaunchKernelGGL(k_push<RICS_TABLE>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
+        case RICS_MLP: hipLaunchKernelGGL(k_push<RICS_MLP>, dim3(st->push_blocks), dim3(PUSH_TPB_MLP), 0, st->stream, a); break;
         default: return fail(st, PIC1D_EINVAL, "RICS backend not available in this build");
     }
     prof_end(st, pk);
@@ -332,8 +347,17 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     *out = nullptr;
     const char* why = validate_config(cfg);
     if (why[0]) return fail(nullptr, PIC1D_EINVAL, why);
-    if (cfg->rics_backend == PIC1D_RICS_MLP && !cfg->mlp_weights)
-        return fail(nullptr, PIC1D_EINVAL, "MLP backend needs mlp_weights");
+    if (cfg->rics_backend == PIC1D_RICS_MLP) {
+        if (!cfg->mlp_weights || !cfg->mlp_norm) return fail(nullptr, PIC1D_EINVAL, "MLP backend needs mlp_weights and mlp_norm");
+        for (int l = 0; l < cfg->n_lines; ++l)
+            if (cfg->lines[l].r_eq != 4.0)
+                return fail(nullptr, PIC1D_EINVAL, "the surrogate network covers the R_max = 4 line only");
+        if (!(cfg->kT_keV >= 0.3 && cfg->kT_keV <= 1.0))
+            return fail(nullptr, PIC1D_EINVAL, "the surrogate network covers kT in [0.3, 1] keV");
+        for (int k = 0; k < 6; ++k)
+            if (!std::isfinite(cfg->mlp_norm[k]) || (k >= 3 && !(cfg->mlp_norm[k] > 0.0f)))
+                return fail(nullptr, PIC1D_EINVAL, "mlp_norm: finite means and positive deviations");
+    }
     pic1d_state* st = new pic1d_state();
     st->cfg = *cfg;
     st->lines_cfg.assign(cfg->lines, cfg->lines + cfg->n_lines);
@@ -359,8 +383,9 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     st->n_cu = prop.multiProcessorCount;
     int occ = 0;
     const void* kp = st->backend == RICS_OFF ? (const void*)k_push<RICS_OFF>
-                   : st->backend == RICS_EXACT ? (const void*)k_push<RICS_EXACT> : (const void*)k_push<RICS_TABLE>;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, PUSH_TPB, 0);
+                   : st->backend == RICS_EXACT ? (const void*)k_push<RICS_EXACT>
+                   : st->backend == RICS_MLP ? (const void*)k_push<RICS_MLP> : (const void*)k_push<RICS_TABLE>;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, st->backend == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB, 0);
     occ = std::max(1, std::min(occ, 8));
     st->push_blocks = st->n_cu * occ;
     st->aux_blocks = st->n_cu * 4;
@@ -420,6 +445,18 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
         INIT_TRY(hipMemcpyAsync(st->layer_target, lt.data(), lt.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     }
     INIT_TRY(hipMemcpyAsync(st->cell_line, cell_line.data(), cell_line.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (st->lay.mlp) {
+        for (int k = 0; k < 6; ++k) st->mlp_norm[k] = cfg->mlp_norm[k];
+        for (int l = 0; l < st->lay.n_lines; ++l) {
+            const std::vector<float>& nd = st->lines[l].nodes;      // {b, mu, x, 0} per node
+            for (size_t i = 0; i < nd.size(); i += 4)
+                if (!(nd[i] >= 0.01f && nd[i] <= 1000.0f))
+                    return bail(PIC1D_EINVAL, "the surrogate network covers B/B_QED in [0.01, 1000] only");
+        }
+        INIT_TRY(hipMemcpyAsync(st->mlp_params, cfg->mlp_weights, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_mlp_pack, dim3(64), dim3(256), 0, s, st->mlp_params, st->mlp_ft, st->mlp_bt, st->mlp_bias);
+        INIT_TRY(hipGetLastError());
+    }
 
     // initial pair plasma
     std::vector<int32_t> alloc0(nseg, 0);
@@ -726,6 +763,7 @@ int pic1d_rics_eval(pic1d_state* st, int32_t line, int64_t n, const float* s_cel
         case RICS_OFF: hipLaunchKernelGGL(k_rics_eval<RICS_OFF>, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
         case RICS_EXACT: hipLaunchKernelGGL(k_rics_eval<RICS_EXACT>, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
         case RICS_TABLE: hipLaunchKernelGGL(k_rics_eval<RICS_TABLE>, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
+        case RICS_MLP: hipLaunchKernelGGL(k_rics_eval_mlp, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
         default: return fail(st, PIC1D_EINVAL, "RICS backend not available in this build");
     }
     HIP_TRY(st, hipGetLastError());

@@ -1,6 +1,7 @@
 // Kernel argument blocks and launch constants shared by kernels.hip and api.hip.
 #pragma once
 
+#include "mlp_dev.h"
 #include "pic1d_dev.h"
 
 namespace pic1d {
@@ -8,6 +9,8 @@ namespace pic1d {
 enum { RICS_OFF = 0, RICS_EXACT = 1, RICS_TABLE = 2, RICS_MLP = 3 };
 
 constexpr int PUSH_TPB = 256;                   // threads per block of the particle kernels
+constexpr int PUSH_TPB_MLP = 256;               // ... with the surrogate network: one block per CU (its
+                                                // weights fill the LDS), one wavefront per SIMD
 constexpr int PUSH_PPT = 8;                     // consecutive particles per thread per tile
 constexpr int CNT_REPL = 64;                    // replicas of every counter (spreads same-address atomics)
 constexpr int PUSH_TILE = 64 * PUSH_PPT;        // particles per tile: one wavefront's work item
@@ -55,6 +58,11 @@ struct PushArgs {
     PhotonRec* photons;        // PHOTON_REPL regions of photon_region slots
     int32_t* n_photons;        // [PHOTON_REPL] fill of each region
     int32_t photon_region;
+    // surrogate network (RICS_MLP): bfloat16 forward tiles and biases, output normalisation
+    const bf16x8* mlp_ft;
+    const float* mlp_bias;
+    float mlp_mean[3], mlp_std[3];
+    float mlp_kTn;             // kT input, normalised to [-1, 1]
 };
 
 struct ConvertArgs {
@@ -191,6 +199,9 @@ struct MomArgs {
 };
 
 template <int BACKEND> __global__ void k_push(PushArgs a);
+__global__ void k_mlp_pack(const float* p, bf16x8* ft, bf16x8* bt, float* bias);
+__global__ void k_rics_eval_mlp(PushArgs a, int line, int64_t n, const float* s_cells, const float* u, float* F,
+                                float* N, float* eps);
 __global__ void k_atmosphere(AtmArgs a);
 __global__ void k_convert(ConvertArgs a);
 __global__ void k_plan(BookArgs b, int advance_step);

@@ -217,12 +217,10 @@ struct Counts {
 // Stochastic regime (b >= b_thr, Sec. 3): after the kick, a scattering event with
 // probability min(Ndot h, 1) from the Philox draw keyed by (step, id); the event
 // emits eps = gamma (1 - (1+2b)^-1/2) and leaves gamma / (1+2b)^1/2 (Appendix A).
-template <int BACKEND>
 __device__ __forceinline__ float stochastic_step(const PushArgs& a, const LineDev& L, const TileCtx& T, int line,
-                                              int64_t k, int c0, float o0, float u, const PartGeo& pg,
+                                              int64_t k, int c0, float o0, float u, const Geo& g, float ndot,
                                               Counts& cnt) {
-    const Geo& g = pg.g;
-    const float lam = rics_N<BACKEND>(a, L, u, pg) * L.h;
+    const float lam = ndot * L.h;
     if (lam > 1.0f) ++cnt.clipped;
     if (!(lam > 0.0f)) return u;
     ++cnt.draws;
@@ -264,6 +262,78 @@ __device__ __forceinline__ float stochastic_step(const PushArgs& a, const LineDe
     return u;
 }
 
+// ---------------------------------------------------------------------------
+// Surrogate-network RICS (RICS_MLP).  The network runs on the matrix cores for
+// the 64 particles of a wavefront at once (four groups of 16 samples), so every
+// lane must reach each evaluation: the callers below are wave-uniform.
+// ---------------------------------------------------------------------------
+struct MlpRics {
+    float F, N;
+};
+
+// F_hat and Ndot_hat at momentum u of a particle with geometry g at arc-length
+// fraction sl (x / n): the network gives G = |F_hat| / |gamma mu - u| and Ndot at
+// (log10 gamma, s/L of the particle or of its mirror point, log10 b, kT);
+// F_hat = (gamma mu - u) G, and both vanish beyond the Planck cutoff.
+__device__ __forceinline__ MlpRics mlp_rics(const PushArgs& a, const bf16x8* W, const float* Wb, float u,
+                                            const Geo& g, float sl) {
+    const int lane = threadIdx.x & 63, g4 = lane >> 4, r = lane & 15;
+    const float ua = fabsf(u);
+    const float gam = fsqrt(fmaf(ua, ua, 1.0f));
+    constexpr float LOG10_2 = 0.301029995663981f;
+    float xn[4];
+    xn[0] = __builtin_amdgcn_logf(gam) * (LOG10_2 * 0.25f) - 1.0f;
+    xn[1] = fmaf(u >= 0.0f ? sl : 1.0f - sl, 2.0f, -1.0f);
+    xn[2] = fmaf(__builtin_amdgcn_logf(g.b) * LOG10_2 + 2.0f, 0.4f, -1.0f);
+    xn[3] = a.mlp_kTn;
+    float o0 = 0.0f, o1 = 0.0f;
+#pragma unroll 1
+    for (int G = 0; G < 4; ++G) {
+        float xg[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xg[k] = __shfl(xn[k], 16 * G + r, 64);
+        const bf16x8 bin = mlp_input_operand(xg, g4);
+        const f32x4 out = mlp_group_forward<false>(W, Wb, bin, nullptr, 0, 0);
+        const float v0 = __shfl(out[0], r, 64), v1 = __shfl(out[1], r, 64);
+        if (g4 == G) {
+            o0 = v0;
+            o1 = v1;
+        }
+    }
+    constexpr float LOG2_10 = 3.32192809488736f;
+    const float y = g.by * frcp(fmaf(-u, g.mu, gam));
+    const bool inside = y <= Y_CUT;
+    MlpRics res;
+    res.F = inside ? fmaf(gam, g.mu, -u) * exp2f(fmaf(a.mlp_std[0], o0, a.mlp_mean[0]) * LOG2_10) : 0.0f;
+    res.N = inside ? exp2f(fmaf(a.mlp_std[1], o1, a.mlp_mean[1]) * LOG2_10) : 0.0f;
+    return res;
+}
+
+// Drag half step with the surrogate force F0 = F(u0) (Sec. 3): damping branch where
+// |F0| tau_min > |u0|; otherwise the implicit midpoint u1 = u0 + (h/4)(F0 + F(u1)),
+// from the explicit start and refined by fixed-point iteration (contraction
+// (h/4)|F'| << 1 on this branch) where (h/2)|F0| exceeds 2^-12 |u0|.  Lanes with
+// active == false return u0 but still take part in the network evaluations.
+__device__ __forceinline__ float mlp_drag_half(const PushArgs& a, const bf16x8* W, const float* Wb, const LineDev& L,
+                                               float u0, float F0, const Geo& g, float sl, float ptilde, bool active,
+                                               bool alive, Counts& cnt) {
+    const bool implicit = fabsf(F0) * L.tau_hat <= fabsf(u0);
+    float u1 = implicit ? fmaf(0.5f * L.h, F0, u0) : fmaf(-(u0 - ptilde), L.damp, u0);
+    cnt.limited += (active && alive && !implicit) ? 1 : 0;
+    bool refine = active && implicit && F0 != 0.0f && 0.5f * L.h * fabsf(F0) > 0x1.0p-12f * fabsf(u0);
+    cnt.newton += (refine && alive) ? 1 : 0;
+#pragma unroll 1
+    for (int it = 0; it < 4; ++it) {
+        if (__ballot(refine) == 0ull) break;
+        const float F1 = mlp_rics(a, W, Wb, u1, g, sl).F;
+        const float un = fmaf(0.25f * L.h, F0 + F1, u0);
+        const bool moved = fabsf(un - u1) > 0x1.0p-24f * fabsf(un);
+        u1 = refine ? un : u1;
+        refine = refine && moved;
+    }
+    return active ? u1 : u0;
+}
+
 // Field and geometry of the cell a lane is working in.  A lane's particles are
 // consecutive in cell order, so the cache is reloaded only when the cell changes.
 // The neighbours of E are clamped at the walls, which makes the gather constant
@@ -296,7 +366,8 @@ template <int BACKEND>
 __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDev& L, const TileCtx& T,
                                                  const CellCache& cc, bool alive, int line, int sp, int64_t k,
                                                  int c0, float o0, float& u, Counts& cnt, int& c1, float& o1,
-                                                 long long& da, long long& db, int& d) {
+                                                 long long& da, long long& db, int& d, const bf16x8* W,
+                                                 const float* Wb) {
     const int n = L.n_cells;
     constexpr bool RICS = BACKEND != RICS_OFF;
 
@@ -313,7 +384,22 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
         kick += (dw <= L.atm_depth) ? gk : 0.0f;
     }
 
-    if (RICS && sp != 3) {
+    if constexpr (BACKEND == RICS_MLP) {
+        if (sp != 3) {            // wave-uniform: a tile holds one species
+            const Geo g = geo_lerp(L, cc.n0, cc.n1, o0);
+            const float sl = (float)(x / (double)n);
+            const bool cont = g.b < L.b_thr;
+            const float pt = g.mu * frsq(fmaxf(fmaf(-g.mu, g.mu, 1.0f), 1e-30f));
+            const MlpRics ra = mlp_rics(a, W, Wb, u, g, sl);
+            u = mlp_drag_half(a, W, Wb, L, u, ra.F, g, sl, pt, cont, alive, cnt);
+            u += kick;
+            const MlpRics rb = mlp_rics(a, W, Wb, u, g, sl);
+            u = mlp_drag_half(a, W, Wb, L, u, rb.F, g, sl, pt, cont, alive, cnt);
+            if (!cont && alive) u = stochastic_step(a, L, T, line, k, c0, o0, u, g, rb.N, cnt);
+        } else {
+            u += kick;
+        }
+    } else if (RICS && sp != 3) {
         const PartGeo pg = part_geo<BACKEND>(L, cc.n0, cc.n1, o0, x, a.ns);
         if (pg.g.b < L.b_thr) {
             // continuous regime: Strang splitting drag h/2, Lorentz kick, drag h/2, both
@@ -324,7 +410,7 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
             u = drag_half<BACKEND>(a, L, u, pg, pt, alive, cnt.limited, cnt.newton);
         } else {
             u += kick;
-            if (alive) u = stochastic_step<BACKEND>(a, L, T, line, k, c0, o0, u, pg, cnt);
+            if (alive) u = stochastic_step(a, L, T, line, k, c0, o0, u, pg.g, rics_N<BACKEND>(a, L, u, pg), cnt);
         }
     } else {
         u += kick;
@@ -381,9 +467,19 @@ __device__ __forceinline__ void wave_sync() {
 // fixed-point current with one atomic per touched cell.  No block-level
 // synchronisation.
 template <int BACKEND>
-__global__ __launch_bounds__(PUSH_TPB) void k_push(PushArgs a) {
-    __shared__ unsigned long long sJ[PUSH_TPB / 64][WW];
-    __shared__ int sH[PUSH_TPB / 64][WW];
+__global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB) void k_push(PushArgs a) {
+    constexpr int TPB = BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB;
+    __shared__ unsigned long long sJ[TPB / 64][WW];
+    __shared__ int sH[TPB / 64][WW];
+    // surrogate weights, staged once per block (the network runs on them for every particle)
+    __shared__ bf16x8 sW[BACKEND == RICS_MLP ? FT_TOTAL * 64 : 1];
+    __shared__ float sWb[BACKEND == RICS_MLP ? MLP_BIAS : 1];
+    if constexpr (BACKEND == RICS_MLP) {
+        // before the error check: every wave of the block reaches the barrier
+        for (int e = threadIdx.x; e < FT_TOTAL * 64; e += TPB) sW[e] = a.mlp_ft[e];
+        for (int e = threadIdx.x; e < MLP_BIAS; e += TPB) sWb[e] = a.mlp_bias[e];
+        __syncthreads();
+    }
     if (a.sc->err != 0) return;
     constexpr bool GEO = BACKEND != RICS_OFF;
     const uint64_t step = a.sc->step;
@@ -508,7 +604,7 @@ __global__ __launch_bounds__(PUSH_TPB) void k_push(PushArgs a) {
             float o1;
             long long da, db;
             advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + q, cc.cell, oq, uq, cnt, c1, o1,
-                                      da, db, d);
+                                      da, db, d, sW, sWb);
             cnt.pushed += alive ? 1 : 0;
             jv1 += alive ? da : 0ll;
             jv0 += (alive && d < 0) ? db : 0ll;
@@ -569,6 +665,7 @@ __global__ __launch_bounds__(PUSH_TPB) void k_push(PushArgs a) {
 template __global__ void k_push<RICS_OFF>(PushArgs);
 template __global__ void k_push<RICS_EXACT>(PushArgs);
 template __global__ void k_push<RICS_TABLE>(PushArgs);
+template __global__ void k_push<RICS_MLP>(PushArgs);
 
 // ---------------------------------------------------------------------------
 // Photon conversion (Sec. 3): every recorded photon with E >= 2 m_e c^2 turns into
@@ -996,5 +1093,26 @@ __global__ __launch_bounds__(256) void k_rics_eval(PushArgs a, int line, int64_t
 template __global__ void k_rics_eval<RICS_OFF>(PushArgs, int, int64_t, const float*, const float*, float*, float*, float*);
 template __global__ void k_rics_eval<RICS_EXACT>(PushArgs, int, int64_t, const float*, const float*, float*, float*, float*);
 template __global__ void k_rics_eval<RICS_TABLE>(PushArgs, int, int64_t, const float*, const float*, float*, float*, float*);
+
+// The surrogate at n points (one per lane; the whole wavefront evaluates the
+// network together, lanes past n on a dummy point).
+__global__ __launch_bounds__(256) void k_rics_eval_mlp(PushArgs a, int line, int64_t n, const float* s_cells,
+                                                       const float* uin, float* F, float* N, float* eps) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = i < n;
+    const LineDev L = a.lines[line];
+    const float s = ok ? fminf(fmaxf(s_cells[i], 0.0f), (float)L.n_cells) : 0.5f;
+    const int c0 = min((int)floorf(s), L.n_cells - 1);
+    const float o0 = s - (float)c0;
+    const double x = (double)c0 + (double)o0;
+    const Geo g = geo_lerp(L, a.nodes[L.node_base + c0], a.nodes[L.node_base + c0 + 1], o0);
+    const float u = ok ? uin[i] : 0.0f;
+    const MlpRics rr = mlp_rics(a, a.mlp_ft, a.mlp_bias, u, g, (float)(x / (double)L.n_cells));
+    if (ok) {
+        F[i] = rr.F;
+        N[i] = rr.N;
+        eps[i] = photon_energy(fsqrt(fmaf(u, u, 1.0f)), g.b);
+    }
+}
 
 }  // namespace pic1d

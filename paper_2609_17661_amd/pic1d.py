@@ -196,6 +196,10 @@ class Pic1D:
         c.workspace = ctypes.c_void_p(self.workspace.data_ptr())
         c.workspace_bytes = n.value
         c.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        if mlp_weights is None:
+            mlp_weights = self.cfg.get("mlp_params")
+        if mlp_norm is None:
+            mlp_norm = self.cfg.get("mlp_norm")
         if mlp_weights is not None:
             self._mlp = np.ascontiguousarray(mlp_weights, dtype=np.float32)
             c.mlp_weights = ctypes.c_void_p(self._mlp.ctypes.data)

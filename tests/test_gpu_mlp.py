@@ -126,3 +126,96 @@ def test_training_on_the_gpu_reduces_the_loss():
     mean, std = omlp.normalisation(O)
     assert np.allclose(r["norm"][:3], mean, rtol=1e-5, atol=1e-5)
     assert np.allclose(r["norm"][3:], std, rtol=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# the surrogate inside the pusher (RICS backend "mlp")
+# ---------------------------------------------------------------------------
+def _pusher_network(seed):
+    """Random weights (float32 values) with a small output layer, and the target
+    normalisation of the oracle's sample stream: drag of physical size, both
+    branches of the limiter and stochastic events all occur."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for li, (o, i) in enumerate(omlp.LAYERS):
+        s = 0.15 if li == len(omlp.LAYERS) - 1 else 1.0
+        parts.append((rng.uniform(-1, 1, (o, i)) * s * omlp.glorot_bound(o, i), rng.uniform(-0.1, 0.1, o)))
+    p = omlp.pack(parts).astype(np.float32).astype(np.float64)
+    _, O, _ = omlp.training_samples(seed=seed, n=4096)
+    mean, std = omlp.normalisation(O)
+    norm = np.concatenate([mean, std]).astype(np.float32).astype(np.float64)
+    return p, norm
+
+
+def _mlp_cfg(seed, **kw):
+    from paper_2609_17661_amd import workloads
+    p, norm = _pusher_network(seed)
+    cfg = workloads.small(r_eq=4.0, rics="mlp", **kw)
+    cfg["mlp_params"] = p
+    cfg["mlp_norm"] = norm
+    return cfg
+
+
+def test_rics_eval_of_the_surrogate_matches_oracle():
+    import torch
+    from oracle import pic
+    from paper_2609_17661_amd import Pic1D
+
+    from . import parity
+    cfg = _mlp_cfg(51, n_cells=400, ppc=1, init="empty")
+    sim = Pic1D(cfg)
+    st = pic.State(parity.oracle_config(cfg))
+    ln = st.lines[0]
+    rng = np.random.default_rng(52)
+    n = 5001
+    s = rng.uniform(0, 400, n).astype(np.float32)
+    lg = rng.uniform(0, 6, n)
+    u = (np.where(rng.random(n) < 0.5, -1.0, 1.0) * np.sqrt(np.maximum(10 ** (2 * lg) - 1, 0))).astype(np.float32)
+    _print("mlp rics_eval", n)
+    F, N, eps = (t.cpu().numpy().astype(np.float64) for t in sim.rics_eval(0, torch.from_numpy(s), torch.from_numpy(u)))
+    xs = s.astype(np.float64)
+    uu = u.astype(np.float64)
+    b, mu, xr, _ = ln.geometry_at(xs)
+    force, _, rate = ln.rics_funcs(xs, b, mu, xr)
+    Fo, No = force(uu), rate(uu)
+    # network outputs agree to ~OUT_TOL; 10^(mean + std out) turns that into a relative error of
+    # ln(10) std OUT_TOL; float32 inputs, exp2 of arguments up to ~100 and the factor
+    # (gamma mu - u) (condition number cond, as for the closed form) add a few float32 ulps each
+    gam = np.sqrt(1 + uu * uu)
+    cond = (gam * np.abs(mu) + np.abs(uu)) / np.maximum(np.abs(gam * mu - uu), 1e-300)
+    tolF = np.log(10) * cfg["mlp_norm"][3] * OUT_TOL + 1e-5 + 2e-7 * cond
+    tolN = np.log(10) * cfg["mlp_norm"][4] * OUT_TOL + 1e-5
+    nz = Fo != 0
+    relF = np.abs(F - Fo)[nz] / np.abs(Fo)[nz]
+    relN = np.abs(N - No)[No > 0] / No[No > 0]
+    _print("F rel max", relF.max(), "N rel max", relN.max(), "zeros", np.sum(~nz))
+    assert np.all(relF <= tolF[nz])
+    assert np.all(relN <= tolN)
+    assert np.array_equal(F[~nz], Fo[~nz])          # beyond the Planck cutoff both are exactly zero
+
+
+@pytest.mark.parametrize("kw", [dict(init="hot", gamma_max=3e3, pairs=True),
+                                dict(init="cold", pairs=False, ppc=24)])
+def test_step_parity_with_the_surrogate(kw):
+    from paper_2609_17661_amd import Pic1D
+
+    from . import parity
+    args = dict(n_cells=96, ppc=12)
+    args.update(kw)
+    cfg = _mlp_cfg(61, **args)
+    ocfg = parity.oracle_config(cfg)
+    sim = Pic1D(cfg)
+    _print("mlp step parity", kw)
+    total = dict(compared=0, excused=0)
+    for k in range(3):
+        before = parity.snapshot(sim)
+        sim.step(1)
+        after = parity.snapshot(sim)
+        rep, st = parity.compare_step(ocfg, before, after)
+        _print(f"  step {k}: {rep} {st.counters[0]}")
+        total["compared"] += rep["compared"]
+        total["excused"] += rep["excused"]
+        sim.step(2)
+    assert total["compared"] > 0
+    assert total["excused"] <= max(3, 1e-3 * total["compared"])
+    assert sim.moments(0)["gauss_residual"] <= 1e-6
