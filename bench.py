@@ -1,20 +1,28 @@
 """Benchmark: particle-steps/s of the 1D PIC hot path (push + RICS drag + deposit +
-pairs + atmosphere + Ampere) on one MI355X, with the push kernel's HBM roofline
-and the FP64 oracle timed on the host as a CPU baseline.
+pairs + atmosphere + Ampere) on one MI355X, with the push kernel's roofline, the
+surrogate-network path beside the table and exact paths, and the FP64 oracle
+timed on the host as a CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--backend table|exact|off]
-                    [--workload cfg2|cfg1] [--no-cpu-baseline]
+                    [--workload cfg2|cfg1] [--no-cpu-baseline] [--no-surrogate]
     python bench.py --copy-calibration     # plain 256 MiB device copy, for HBM counters
 
-Workload (default): the R_max = 30 line with 65,536 cells, 200 e-/e+ per cell
-each (2.6e7 particles), surface atmosphere with ions at m_i/m_e = 100, pairs on
-with curvature conversion, capacity for 1e8 particles, TABLE RICS backend.
-Inputs are synthetic (Philox initial plasma) and resident in HBM before the
+Plain path (the headline `value`): the R_max = 30 line with 65,536 cells, 200
+e-/e+ per cell each (2.6e7 particles), surface atmosphere with ions at
+m_i/m_e = 100, pairs on with curvature conversion, capacity for 1e8 particles,
+TABLE RICS backend.
+
+Surrogate path (`surrogate_vs_table`): the network is trained on the GPU by the
+library (outside the timed region), then the R_max = 4 line of its training
+geometry at the same particle count (65,536 cells x 200 hot e-/e+ per cell) is
+stepped with the TABLE, EXACT and MLP backends in turn.  The network's error is
+judged against the library's EXACT backend at the workload's particles.
+
+Inputs are synthetic (Philox initial plasma) and resident in HBM before each
 timed region.  One JSON line is printed.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -24,9 +32,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+BF16_PEAK = 2.5e15         # MI355X dense bf16 MFMA, FLOP/s
 BYTES_PER_PARTICLE = 24    # cell, offset, u: read 12 B + write 12 B
 BYTES_PER_DRAW = 8         # 64-bit id read for a Philox event draw
 BYTES_PER_CHILD = 20       # appended particle: cell, offset, u, id
+MLP_FLOP_PER_EVAL = 2 * (4 * 128 + 3 * 128 * 128 + 128 * 3)   # multiply-adds of one network evaluation, x2
+MLP_MFMA_PER_GROUP = 308   # v_mfma_f32_16x16x32_bf16 per 16 evaluations (three bfloat16 terms per activation)
 PROFILE_HBM = os.path.join(ROOT, "profiles", "k_push_cfg2_table_hbm.md")
 CAL_BYTES = 256 << 20      # bytes read (and written) by one calibration copy
 
@@ -79,7 +90,7 @@ def copy_calibration():
           flush=True)
 
 
-def cpu_baseline(cfg, sample_ppc=20, steps=3):
+def cpu_baseline(cfg, sample_ppc=40, steps=6):
     """The oracle (FP64 numpy, single thread) on the same line with fewer particles per cell."""
     from threadpoolctl import threadpool_limits
 
@@ -104,6 +115,111 @@ def cpu_baseline(cfg, sample_ppc=20, steps=3):
                 seconds=dt)
 
 
+def timed_run(sim, steps, warmup):
+    """Warm up, then time `steps` steps with HIP events on the library's stream;
+    per-kernel event timing (pic1d_profile) is on during the timed steps."""
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    m0 = sim.moments(0)
+    sim.profile(True)
+    stream = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = sim.profile_read()
+    sim.profile(False)
+    m1 = sim.moments(0)
+    c0, c1 = m0["counters"], m1["counters"]
+    cnt = {k: c1[k] - c0[k] for k in c1}
+    push = prof["push"]
+    push_avg_s = push["ms"] / max(push["launches"], 1) * 1e-3
+    return dict(ms=ms, value=cnt["pushed"] / (ms * 1e-3), ms_per_step=ms / steps, counters=cnt,
+                push_avg_s=push_avg_s, launches=push["launches"],
+                kernels_ms={k: v["ms"] / max(v["launches"], 1) for k, v in prof.items() if v["launches"]},
+                m0=m0, m1=m1)
+
+
+def hbm_bytes_per_launch(r):
+    c = r["counters"]
+    return (BYTES_PER_PARTICLE * c["pushed"] + BYTES_PER_DRAW * c["draws"] +
+            BYTES_PER_CHILD * 2 * c["pairs_created"]) / max(r["launches"], 1)
+
+
+def surrogate_comparison(steps, warmup, mlp_steps):
+    """Train the network, then step the CFG4 line with the table, exact and MLP backends."""
+    import numpy as np
+    import torch
+
+    from paper_2609_17661_amd import Pic1D, pic1d, workloads
+
+    t0 = time.perf_counter()
+    tr = pic1d.mlp_train(seed=0, n_samples=1 << 22, batch=8192, steps=mlp_steps, lr=2e-3, lr_final=2e-6, n_loss=10)
+    out = {"training": {"steps": mlp_steps, "batch": 8192, "pool": 1 << 22, "seconds": tr["seconds"],
+                        "loss_first": tr["loss_first"], "loss_last": tr["loss_last"]}}
+    print(f"# surrogate trained in {time.perf_counter() - t0:.1f} s, loss {tr['loss_last']:.3g}", file=sys.stderr,
+          flush=True)
+    res = {}
+    for backend in ("table", "exact", "mlp"):
+        cfg = dict(workloads.CFG4)
+        cfg["rics"] = backend
+        if backend == "mlp":
+            cfg["mlp_params"] = tr["params"]
+            cfg["mlp_norm"] = tr["norm"]
+        sim = Pic1D(cfg, device="cuda:0")
+        r = timed_run(sim, steps, warmup)
+        entry = {"value": r["value"], "ms_per_step": r["ms_per_step"], "k_push_ms": r["push_avg_s"] * 1e3,
+                 "kernels_ms": r["kernels_ms"], "events": r["counters"]["events"],
+                 "pairs_created": r["counters"]["pairs_created"]}
+        if backend == "mlp":
+            evals = r["counters"]["mlp_evals"] / max(r["launches"], 1)
+            achieved = evals * MLP_FLOP_PER_EVAL / r["push_avg_s"]
+            executed = evals / 16 * MLP_MFMA_PER_GROUP * (16 * 16 * 32 * 2) / r["push_avg_s"]
+            entry["roofline"] = {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12,
+                                 "unit": "TFLOP/s", "frac": achieved / BF16_PEAK, "kernel": "k_push<mlp>",
+                                 "evals_per_launch": evals, "flop_per_eval": MLP_FLOP_PER_EVAL,
+                                 "executed_mfma_tflops": executed / 1e12, "executed_frac": executed / BF16_PEAK}
+            # network error against the library's exact backend at this workload's particles
+            p = sim.get_particles(0, 0)
+            n = min(200000, p["cell"].size)
+            s = torch.from_numpy((p["cell"][:n] + p["off"][:n]).astype(np.float32))
+            u = torch.from_numpy(p["u"][:n].astype(np.float32))
+            Fm, Nm, _ = (t.cpu().numpy().astype(np.float64) for t in sim.rics_eval(0, s, u))
+            ecfg = dict(workloads.CFG4)
+            ecfg["rics"] = "exact"
+            ecfg["lines"] = [dict(ecfg["lines"][0], init="empty", ppc_init=0, capacity=[256, 256, 0, 0])]
+            esim = Pic1D(ecfg, device="cuda:0")
+            Fe, Ne, _ = (t.cpu().numpy().astype(np.float64) for t in esim.rics_eval(0, s, u))
+            esim.close()
+            h = cfg["cfl"] if "cfl" in cfg else 0.5
+            h *= 9.004239 / cfg["lines"][0]["n_cells"]        # one step in R*/c on the R_max = 4 line
+            uu = np.abs(u.numpy().astype(np.float64))
+            sig = np.abs(Fe) * h >= 1e-9 * np.maximum(uu, 1e-30)
+            eF = np.abs(Fm - Fe)[sig] / np.abs(Fe)[sig]
+            sigN = Ne * h > 1e-9
+            eN = np.abs(Nm - Ne)[sigN] / Ne[sigN]
+            entry["error_vs_exact"] = {
+                "F_median": float(np.median(eF)), "F_p99": float(np.quantile(eF, 0.99)), "F_max": float(eF.max()),
+                "Ndot_median": float(np.median(eN)) if eN.size else None,
+                "Ndot_p99": float(np.quantile(eN, 0.99)) if eN.size else None,
+                "sample": f"{n} e- of the workload after the timed steps, where |F| h >= 1e-9 |u|"}
+        res[backend] = entry
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        print(f"# {backend}: {entry['value']:.3g} particle-steps/s", file=sys.stderr, flush=True)
+    out.update(res)
+    out["workload"] = ("cfg4: R_max=4 line (the network's training geometry), 65536 cells, 200 hot e-/e+ per cell "
+                       "(gamma log-uniform to 1e4), pairs (immediate)")
+    out["mlp_over_table"] = res["mlp"]["value"] / res["table"]["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +228,9 @@ def main():
     ap.add_argument("--backend", default="table", choices=["table", "exact", "off"])
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=10)
+    ap.add_argument("--mlp-train-steps", type=int, default=50000)
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -131,41 +250,19 @@ def main():
     cfg["rics"] = args.backend
     sim = Pic1D(cfg, device="cuda:0")
     print(f"# init done: {cfg['lines'][0]}", file=sys.stderr, flush=True)
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    m0 = sim.moments(0)
-    sim.profile(True)
-    stream = sim.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    sim.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    prof = sim.profile_read()
-    sim.profile(False)
-    m1 = sim.moments(0)
-    c0, c1 = m0["counters"], m1["counters"]
-    pushed = c1["pushed"] - c0["pushed"]
-    draws = c1["draws"] - c0["draws"]
-    children = 2 * (c1["pairs_created"] - c0["pairs_created"])
-    value = pushed / (ms * 1e-3)
-    push = prof["push"]
-    push_avg_s = push["ms"] / max(push["launches"], 1) * 1e-3
-    bytes_per_launch = (BYTES_PER_PARTICLE * pushed + BYTES_PER_DRAW * draws + BYTES_PER_CHILD * children) / max(
-        push["launches"], 1)
-    achieved = bytes_per_launch / push_avg_s
+    r = timed_run(sim, args.steps, args.warmup)
+    bytes_per_launch = hbm_bytes_per_launch(r)
+    achieved = bytes_per_launch / r["push_avg_s"]
     traffic = measured_traffic(args.backend, args.workload)     # HBM bytes per k_push launch (rocprofv3)
+    m0, m1 = r["m0"], r["m1"]
     res = {
         "metric": "particle-steps/s (push+RICS drag+deposit+pairs)",
-        "value": value,
+        "value": r["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -179,13 +276,18 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK,
                      "traffic": traffic,
-                     "kernel": "k_push", "avg_ms": push_avg_s * 1e3,
+                     "kernel": "k_push", "avg_ms": r["push_avg_s"] * 1e3,
                      "bytes_per_launch": bytes_per_launch, "traffic_unit": "bytes/launch",
                      "traffic_over_algorithmic": traffic / bytes_per_launch if traffic else None},
-        "kernels_ms": {k: v["ms"] / max(v["launches"], 1) for k, v in prof.items() if v["launches"]},
-        "counters": {k: c1[k] - c0[k] for k in c1},
+        "kernels_ms": r["kernels_ms"],
+        "counters": r["counters"],
         "gauss_residual": m1["gauss_residual"],
     }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_surrogate:
+        res["surrogate_vs_table"] = surrogate_comparison(args.surrogate_steps, 3, args.mlp_train_steps)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(res), flush=True)

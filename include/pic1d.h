@@ -88,6 +88,7 @@ enum { PIC1D_CNT_EVENTS = 0,          /* stochastic RICS events                 
        PIC1D_CNT_ATM = 7,             /* atmosphere (e-, ion) pairs injected    */
        PIC1D_CNT_PUSHED = 8,          /* particle-steps pushed                  */
        PIC1D_CNT_DRAWS = 9,           /* Philox draws of event decisions        */
+       PIC1D_CNT_MLP_EVALS = 10,      /* surrogate-network evaluations (one per lane and call) */
        PIC1D_NCOUNTERS = 16 };
 
 typedef struct {
@@ -150,7 +151,7 @@ typedef struct {
     double energy_kinetic;    /* sum m c^2 (gamma - 1), code units            */
     double energy_field;      /* sum E^2 / 8 pi, code units                   */
     int64_t count[4];         /* live particles per species                   */
-    int64_t counters[16];     /* PIC1D_CNT_* since init (slots 10-15 reserved) */
+    int64_t counters[16];     /* PIC1D_CNT_* since init (slots 11-15 reserved) */
     int64_t step;             /* steps taken since init                       */
     int64_t avg_steps;        /* steps in the averages                        */
 } pic1d_moments_out;

@@ -211,7 +211,7 @@ __device__ __forceinline__ bool append_particle(const PushArgs& a, int seg, int 
 
 struct Counts {
     int events = 0, pairs = 0, escaped = 0, absorbed = 0, clipped = 0, limited = 0, newton = 0, pushed = 0,
-        draws = 0;
+        draws = 0, mlp = 0;
 };
 
 // Stochastic regime (b >= b_thr, Sec. 3): after the kick, a scattering event with
@@ -276,8 +276,9 @@ struct MlpRics {
 // (log10 gamma, s/L of the particle or of its mirror point, log10 b, kT);
 // F_hat = (gamma mu - u) G, and both vanish beyond the Planck cutoff.
 __device__ __forceinline__ MlpRics mlp_rics(const PushArgs& a, const bf16x8* W, const float* Wb, float u,
-                                            const Geo& g, float sl) {
+                                            const Geo& g, float sl, int& n_eval) {
     const int lane = threadIdx.x & 63, g4 = lane >> 4, r = lane & 15;
+    ++n_eval;
     const float ua = fabsf(u);
     const float gam = fsqrt(fmaf(ua, ua, 1.0f));
     constexpr float LOG10_2 = 0.301029995663981f;
@@ -325,7 +326,7 @@ __device__ __forceinline__ float mlp_drag_half(const PushArgs& a, const bf16x8* 
 #pragma unroll 1
     for (int it = 0; it < 4; ++it) {
         if (__ballot(refine) == 0ull) break;
-        const float F1 = mlp_rics(a, W, Wb, u1, g, sl).F;
+        const float F1 = mlp_rics(a, W, Wb, u1, g, sl, cnt.mlp).F;
         const float un = fmaf(0.25f * L.h, F0 + F1, u0);
         const bool moved = fabsf(un - u1) > 0x1.0p-24f * fabsf(un);
         u1 = refine ? un : u1;
@@ -390,10 +391,10 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
             const float sl = (float)(x / (double)n);
             const bool cont = g.b < L.b_thr;
             const float pt = g.mu * frsq(fmaxf(fmaf(-g.mu, g.mu, 1.0f), 1e-30f));
-            const MlpRics ra = mlp_rics(a, W, Wb, u, g, sl);
+            const MlpRics ra = mlp_rics(a, W, Wb, u, g, sl, cnt.mlp);
             u = mlp_drag_half(a, W, Wb, L, u, ra.F, g, sl, pt, cont, alive, cnt);
             u += kick;
-            const MlpRics rb = mlp_rics(a, W, Wb, u, g, sl);
+            const MlpRics rb = mlp_rics(a, W, Wb, u, g, sl, cnt.mlp);
             u = mlp_drag_half(a, W, Wb, L, u, rb.F, g, sl, pt, cont, alive, cnt);
             if (!cont && alive) u = stochastic_step(a, L, T, line, k, c0, o0, u, g, rb.N, cnt);
         } else {
@@ -440,11 +441,12 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
 }
 
 __device__ __forceinline__ void counts_flush(unsigned long long* counters, int line, Counts& c) {
-    const int v[9] = {c.events, c.pairs, c.escaped, c.absorbed, c.clipped, c.limited, c.newton, c.pushed, c.draws};
-    const int slot[9] = {0, 1, 2, 3, 4, 5, 6, 8, 9};
+    const int v[10] = {c.events, c.pairs, c.escaped, c.absorbed, c.clipped, c.limited, c.newton, c.pushed, c.draws,
+                       c.mlp};
+    const int slot[10] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 10};
     const size_t rep = ((size_t)line * CNT_REPL + (blockIdx.x & (CNT_REPL - 1))) * NCOUNT;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < 10; ++i) {
         const int s = wave_sum_i(v[i]);
         if ((threadIdx.x & 63) == 0 && s != 0) atomicAdd(&counters[rep + slot[i]], (unsigned long long)s);
     }
@@ -1107,7 +1109,8 @@ __global__ __launch_bounds__(256) void k_rics_eval_mlp(PushArgs a, int line, int
     const double x = (double)c0 + (double)o0;
     const Geo g = geo_lerp(L, a.nodes[L.node_base + c0], a.nodes[L.node_base + c0 + 1], o0);
     const float u = ok ? uin[i] : 0.0f;
-    const MlpRics rr = mlp_rics(a, a.mlp_ft, a.mlp_bias, u, g, (float)(x / (double)L.n_cells));
+    int n_eval = 0;
+    const MlpRics rr = mlp_rics(a, a.mlp_ft, a.mlp_bias, u, g, (float)(x / (double)L.n_cells), n_eval);
     if (ok) {
         F[i] = rr.F;
         N[i] = rr.N;

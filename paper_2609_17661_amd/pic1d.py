@@ -56,7 +56,7 @@ class CMoments(ctypes.Structure):
 
 
 COUNTER_NAMES = ("events", "pairs_created", "photons_escaped", "absorbed", "psc_clipped", "limited",
-                 "newton", "atm_injected", "pushed", "draws")
+                 "newton", "atm_injected", "pushed", "draws", "mlp_evals")
 
 
 class CProfile(ctypes.Structure):

@@ -12,6 +12,13 @@ at the sizes of the benchmark configurations:
 * CFG2      one line, R_max = 30, 65,536 cells, 200 e-/e+ per cell each,
             surface atmosphere with ions at m_i/m_e = 100, pairs on with
             curvature conversion, capacity for 1e8 particles, 20,000 steps.
+* CFG4      the surrogate comparison: the R_max = 4 line of the network's
+            training geometry at the particle count of CFG2 (65,536 cells,
+            200 e-/e+ per cell each), gamma log-uniform in [1, 1e4] so that
+            the drag and the scattering events are active, pairs on up to
+            n_max = 3 n0 per cell (at this resolution almost every lepton with
+            gamma >~ 1e3 in the b >= 0.1 region scatters each step, and the
+            cascade is held by n_max).
 """
 
 CFG1 = dict(
@@ -32,6 +39,13 @@ CFG2 = dict(
                 capacity=[46_000_000, 46_000_000, 4_000_000, 4_000_000])],
 )
 CFG2_STEPS = 20000
+
+CFG4 = dict(
+    rics="table", table_nlg=256, table_ns=512, kT_keV=0.5, j_twist=0.5, ppc0=200.0, pairs=True,
+    conversion="immediate", nmax_over_n0=3.0, seed=0, sort_interval=20,
+    lines=[dict(r_eq=4.0, n_cells=65536, ppc_init=200, init="hot", init_gamma_max=1.0e4,
+                capacity=[40_000_000, 40_000_000, 0, 0])],
+)
 
 
 def small(r_eq=4.0, n_cells=96, ppc=16, init="hot", **kw):

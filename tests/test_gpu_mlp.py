@@ -219,3 +219,65 @@ def test_step_parity_with_the_surrogate(kw):
     assert total["compared"] > 0
     assert total["excused"] <= max(3, 1e-3 * total["compared"])
     assert sim.moments(0)["gauss_residual"] <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# what the trained network gains
+# ---------------------------------------------------------------------------
+def _continued_targets(X):
+    """o1, o2, o3 of the oracle's definitions, continued past the Planck cutoff in log
+    form (finite for every y) so that a table can hold them at every node."""
+    from oracle import rics
+    X = np.asarray(X, dtype=np.float64)
+    lg, sl, lb, kT = X[:, 0], X[:, 1], X[:, 2], X[:, 3]
+    gam = 10.0 ** lg
+    u = np.sqrt(np.maximum(gam * gam - 1.0, 0.0))
+    b = 10.0 ** lb
+    mu, x = omlp.line_geometry(sl)
+    y = rics.resonance_y(u, b, mu, kT)
+    A_F, A_N = rics.prefactors(kT)
+    lp = -np.log10(-np.expm1(-y)) - y / np.log(10.0)          # log10 of 1/(e^y - 1)
+    o1 = np.log10(A_F / (x * x)) + 3.0 * np.log10(y) + lp
+    o2 = np.log10(A_N / (x * x * gam)) + 2.0 * np.log10(y) + lp
+    return np.stack([o1, o2, np.log10(rics.photon_energy(u, b))], axis=1)
+
+
+def _multilinear_table_error(n, X, O):
+    """Relative errors of a 4D multilinear table with n nodes per input axis over the network's box."""
+    axes = [np.linspace(lo, hi, n) for lo, hi in zip(omlp.IN_LO, omlp.IN_HI)]
+    grid = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 4)
+    V = _continued_targets(grid).reshape(n, n, n, n, 3)
+    f = (X - omlp.IN_LO) / (omlp.IN_HI - omlp.IN_LO) * (n - 1)
+    i0 = np.clip(np.floor(f).astype(int), 0, n - 2)
+    w = f - i0
+    out = np.zeros((X.shape[0], 3))
+    for corner in range(16):
+        wt = np.ones(X.shape[0])
+        idx = []
+        for d in range(4):
+            bit = (corner >> d) & 1
+            wt = wt * (w[:, d] if bit else 1.0 - w[:, d])
+            idx.append(i0[:, d] + bit)
+        out += wt[:, None] * V[idx[0], idx[1], idx[2], idx[3]]
+    return np.abs(out - O) * np.log(10.0)
+
+
+def test_trained_network_beats_a_table_of_equal_storage():
+    """The network (50,563 parameters) against a 4D multilinear table holding more values
+    (12^4 nodes x 3 outputs = 62,208) over the same inputs, on held-out samples of the
+    sample stream scored against the oracle's exact targets: errors of 10^o, relative."""
+    import torch
+    _print("mlp training for the comparison")
+    r = pic1d.mlp_train(seed=3, n_samples=1 << 20, batch=8192, steps=20000, lr=2e-3, lr_final=2e-6, n_loss=5)
+    _print("loss", r["loss_first"], "->", r["loss_last"], "in", r["seconds"], "s")
+    X, O, _ = omlp.training_samples(seed=3, n=20000, first=1 << 40)
+    out = pic1d.mlp_forward(torch.from_numpy(r["params"]).cuda(), torch.from_numpy(X).cuda()).cpu().numpy()
+    o = out.astype(np.float64) * r["norm"][3:].astype(np.float64) + r["norm"][:3].astype(np.float64)
+    e_net = np.abs(o - O) * np.log(10.0)
+    e_tab = _multilinear_table_error(12, X.astype(np.float64), O)
+    for k, name in enumerate(("F/(gamma mu - u)", "Ndot", "eps")):
+        _print(f"{name}: network median {np.median(e_net[:, k]):.3e} p99 {np.quantile(e_net[:, k], 0.99):.3e}; "
+               f"table median {np.median(e_tab[:, k]):.3e} p99 {np.quantile(e_tab[:, k], 0.99):.3e}")
+    for k in (0, 1):
+        assert np.median(e_net[:, k]) < 0.5 * np.median(e_tab[:, k])
+        assert np.quantile(e_net[:, k], 0.99) < 0.1 * np.quantile(e_tab[:, k], 0.99)
