@@ -224,6 +224,32 @@ typedef struct {
 int pic1d_profile(pic1d_state* st, int32_t enable);
 int pic1d_profile_read(pic1d_state* st, pic1d_profile_out* out);
 
+/* Capture the step sequence in HIP graphs of steps_per_graph steps (rounded up
+ * to a multiple of sort_interval) and replay them in pic1d_step; 0 returns to
+ * eager launches.  Graphs are captured on first use (one per live particle
+ * buffer set) on a private stream and replayed on the config's stream; steps
+ * before the next multiple of the graph length, remainders and profiled steps
+ * run eagerly.  The results are the same as eager stepping.
+ * Errors: EINVAL. */
+int pic1d_set_graph(pic1d_state* st, int32_t steps_per_graph);
+
+typedef struct {
+    int32_t push_blocks_per_cu;  /* blocks of the particle kernel per compute unit */
+    int32_t xcd_walk;            /* 1: tiles walked in one contiguous range per XCD */
+    int32_t sort_interval;       /* steps between cell sorts                       */
+    int32_t n_trials;            /* launch shapes timed                            */
+    double ms_per_step_before;   /* with the shape the state had                   */
+    double ms_per_step_after;    /* with the chosen shape                          */
+} pic1d_tune_out;
+
+/* Autotuner of the launch shape: times trial_steps real steps (at least one
+ * sort cycle) for each candidate -- push blocks per CU in {1,2,3,4,6,8}, the
+ * XCD-aware tile walk on/off, sort_interval in {10,25,50,100} -- one knob at a
+ * time, and keeps the fastest.  The trial steps advance the simulation; the
+ * physics does not depend on these choices (particle order and launch shape do
+ * not change any result).  Errors: EINVAL, ESTATE, ECAPACITY, ENONFINITE. */
+int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out);
+
 /* Evaluate the configured RICS backend of one line at n points, exactly as
  * the pusher does (float32): device arrays s_cells[n] (arc length in cells,
  * geometry interpolated from the nodes) and u[n]; outputs device arrays

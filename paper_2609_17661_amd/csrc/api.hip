@@ -88,11 +88,26 @@ struct pic1d_state {
     float mlp_norm[6] = {0, 0, 0, 1, 1, 1};
     // per-kernel event timing (pic1d_profile)
     int prof_on = 0;
+    // launch shape (tunable) and captured step graphs
+    int xcd_walk = 1;
+    int push_bpc = 0;                              // push blocks per CU
+    int graph_steps = 0;                           // requested steps per graph; 0 = eager
+    int graph_len = 0;                             // steps per graph (a multiple of sort_interval)
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // by the live buffer set at the graph's start
+    hipStream_t cap_stream = nullptr;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kernel;     // kernel id of each recorded pair (pool index 2k, 2k+1)
     double prof_ms[8] = {0};
     int64_t prof_n[8] = {0};
+    void drop_graphs() {
+        for (auto& g : gexec) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    }
     ~pic1d_state() {
+        drop_graphs();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
 };
@@ -217,6 +232,7 @@ PushArgs push_args(pic1d_state* st) {
     a.table = st->table; a.hist[0] = st->hist[0]; a.hist[1] = st->hist[1];
     a.pair_step = st->pair_step; a.counters = st->counters; a.sc = st->sc;
     a.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); a.key1 = (uint32_t)(st->cfg.seed >> 32);
+    a.xcd_walk = st->xcd_walk;
     a.mlp_ft = st->mlp_ft; a.mlp_bias = st->mlp_bias;
     for (int k = 0; k < 3; ++k) { a.mlp_mean[k] = st->mlp_norm[k]; a.mlp_std[k] = st->mlp_norm[3 + k]; }
     a.mlp_kTn = (float)((st->cfg.kT_keV - 0.3) * (2.0 / 0.7) - 1.0);
@@ -487,12 +503,16 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     return PIC1D_OK;
 }
 
-int pic1d_step(pic1d_state* st, int32_t n_steps) {
-    if (!st || n_steps < 0) return fail(st, PIC1D_EINVAL, "bad arguments");
-    if (st->frozen) return fail(st, PIC1D_ESTATE, "state frozen by an earlier error");
+}  // extern "C"
+
+namespace {
+
+// Enqueue one step on st->stream: push, conversion, atmosphere, Ampere, plan,
+// and the cell sort every sort_interval steps.
+int enqueue_step(pic1d_state* st) {
     const int nt = st->lay.n_cells;
     FieldArgs f{};
-    for (int32_t i = 0; i < n_steps; ++i) {
+    {
         int rc = launch_push(st);
         if (rc) return rc;
         if (st->cfg.pairs) {
@@ -540,10 +560,173 @@ int pic1d_step(pic1d_state* st, int32_t n_steps) {
             if (rc) return rc;
         }
     }
+    return PIC1D_OK;
+}
+
+// Capture graph_len steps starting from the current buffer set (host_step a
+// multiple of graph_len) on a private stream; the host-side step state is
+// restored afterwards, the graph replays on the caller's stream.
+int capture_graph(pic1d_state* st) {
+    if (!st->cap_stream) HIP_TRY(st, hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking));
+    const hipStream_t user = st->stream;
+    const uint64_t hs = st->host_step;
+    const int cur0 = st->cur, prof = st->prof_on;
+    st->stream = st->cap_stream;
+    st->prof_on = 0;
+    hipGraph_t g = nullptr;
+    int rc = PIC1D_OK;
+    hipError_t e = hipStreamBeginCapture(st->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        for (int i = 0; i < st->graph_len && rc == PIC1D_OK; ++i) rc = enqueue_step(st);
+        const hipError_t e2 = hipStreamEndCapture(st->cap_stream, &g);
+        if (e2 != hipSuccess) e = e2;
+    }
+    st->stream = user;
+    st->host_step = hs;
+    st->cur = cur0;
+    st->prof_on = prof;
+    if (rc != PIC1D_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(st, PIC1D_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&st->gexec[cur0], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        st->gexec[cur0] = nullptr;
+        return fail(st, PIC1D_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return PIC1D_OK;
+}
+
+// Steps per graph for a request: a multiple of the sort interval, so that every
+// replay starts at the same point of the sort cycle.
+int graph_length(const pic1d_state* st, int requested) {
+    if (requested <= 0) return 0;
+    const int S = st->cfg.sort_interval;
+    return S > 0 ? ((requested + S - 1) / S) * S : requested;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic1d_step(pic1d_state* st, int32_t n_steps) {
+    if (!st || n_steps < 0) return fail(st, PIC1D_EINVAL, "bad arguments");
+    if (st->frozen) return fail(st, PIC1D_ESTATE, "state frozen by an earlier error");
+    int32_t i = 0;
+    const int G = st->graph_len;
+    if (G > 0 && !st->prof_on) {
+        // eager up to the next multiple of G, then whole graphs
+        while (i < n_steps && st->host_step % (uint64_t)G != 0) {
+            if (int rc = enqueue_step(st)) return rc;
+            ++i;
+        }
+        const int S = st->cfg.sort_interval;
+        const int flips = S > 0 ? (G / S) & 1 : 0;
+        while (n_steps - i >= G) {
+            if (!st->gexec[st->cur])
+                if (int rc = capture_graph(st)) return rc;
+            HIP_TRY(st, hipGraphLaunch(st->gexec[st->cur], st->stream));
+            st->host_step += (uint64_t)G;
+            st->cur ^= flips;
+            i += G;
+        }
+    }
+    for (; i < n_steps; ++i)
+        if (int rc = enqueue_step(st)) return rc;
     HIP_TRY(st, hipGetLastError());
     const int rc = check_error(st);
     prof_collect(st);
     return rc;
+}
+
+int pic1d_set_graph(pic1d_state* st, int32_t steps_per_graph) {
+    if (!st || steps_per_graph < 0) return fail(st, PIC1D_EINVAL, "bad arguments");
+    st->drop_graphs();
+    st->graph_steps = steps_per_graph;
+    st->graph_len = graph_length(st, steps_per_graph);
+    return PIC1D_OK;
+}
+
+int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out) {
+    if (!st || trial_steps < 1 || !out) return fail(st, PIC1D_EINVAL, "bad arguments");
+    if (st->frozen) return fail(st, PIC1D_ESTATE, "state frozen by an earlier error");
+    hipEvent_t e0, e1;
+    HIP_TRY(st, hipEventCreate(&e0));
+    HIP_TRY(st, hipEventCreate(&e1));
+    const int prof = st->prof_on;
+    st->prof_on = 0;
+    int trials = 0;
+    // time `trial` real steps (at least one sort cycle) with the current shape
+    // eager launches while tuning: graph capture would land in the timed steps
+    auto measure = [&](double& ms_per_step) -> int {
+        st->drop_graphs();
+        st->graph_len = 0;
+        const int S = st->cfg.sort_interval;
+        const int n = std::max(trial_steps, S > 0 ? S : 0);
+        if (int rc = pic1d_step(st, 1)) return rc;           // warm: capture or caches
+        HIP_TRY(st, hipEventRecord(e0, st->stream));
+        if (int rc = pic1d_step(st, n)) return rc;
+        HIP_TRY(st, hipEventRecord(e1, st->stream));
+        HIP_TRY(st, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(st, hipEventElapsedTime(&ms, e0, e1));
+        ms_per_step = ms / n;
+        ++trials;
+        return PIC1D_OK;
+    };
+    double base = 0.0;
+    int rc = measure(base);
+    double best = base;
+    const int occ = std::max(1, st->push_blocks / std::max(st->n_cu, 1));
+    // 1. push blocks per CU
+    const int bpc0 = occ;
+    int best_bpc = bpc0;
+    const int cand_bpc[] = {1, 2, 3, 4, 6, 8};
+    for (int c : cand_bpc) {
+        if (rc || c == bpc0 || c > 2 * occ + 2) continue;
+        st->push_blocks = st->n_cu * c;
+        double t = 0.0;
+        rc = measure(t);
+        if (!rc && t < best) { best = t; best_bpc = c; }
+    }
+    st->push_blocks = st->n_cu * best_bpc;
+    // 2. XCD-aware tile walk on or off
+    if (!rc) {
+        const int x0 = st->xcd_walk;
+        st->xcd_walk = 1 - x0;
+        double t = 0.0;
+        rc = measure(t);
+        if (!rc && t < best) best = t; else st->xcd_walk = x0;
+    }
+    // 3. sort interval (the result does not depend on the particle order)
+    if (!rc) {
+        const int s0 = st->cfg.sort_interval;
+        int best_s = s0;
+        const int cand_s[] = {10, 25, 50, 100};
+        for (int c : cand_s) {
+            if (rc || c == s0) continue;
+            st->cfg.sort_interval = c;
+            double t = 0.0;
+            rc = measure(t);
+            if (!rc && t < best) { best = t; best_s = c; }
+        }
+        st->cfg.sort_interval = best_s;
+    }
+    st->drop_graphs();
+    st->graph_len = graph_length(st, st->graph_steps);
+    st->prof_on = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    out->push_blocks_per_cu = st->push_blocks / std::max(st->n_cu, 1);
+    out->xcd_walk = st->xcd_walk;
+    out->sort_interval = st->cfg.sort_interval;
+    out->n_trials = trials;
+    out->ms_per_step_before = base;
+    out->ms_per_step_after = best;
+    return PIC1D_OK;
 }
 
 int pic1d_profile(pic1d_state* st, int32_t enable) {

@@ -63,6 +63,7 @@ struct PushArgs {
     const float* mlp_bias;
     float mlp_mean[3], mlp_std[3];
     float mlp_kTn;             // kT input, normalised to [-1, 1]
+    int32_t xcd_walk;          // 1: each XCD walks a contiguous range of tiles (its own L2)
 };
 
 struct ConvertArgs {

@@ -51,12 +51,12 @@ __device__ __forceinline__ int find_segment(const int32_t* __restrict__ prefix, 
 // its XCD's range.
 struct WaveWalk {
     int t, end, stride;
-    __device__ WaveWalk(int total) {
+    __device__ WaveWalk(int total, int xcd = 1) {
         const int wpb = blockDim.x >> 6;
         const int nb = gridDim.x >> 3;
         // wave-uniform: keeps every per-tile quantity in scalar registers
         const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        if (nb == 0 || (gridDim.x & 7) != 0) {
+        if (!xcd || nb == 0 || (gridDim.x & 7) != 0) {
             t = blockIdx.x * wpb + wid; end = total; stride = gridDim.x * wpb;
             return;
         }
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB) void
     Counts cnt;
     int cur_line = -1;
     int seg = 0, seg_t0 = 0, seg_t1 = 0;       // segment of the previous tile and its tile range
-    for (WaveWalk ww(total); ww.t < ww.end; ww.t += ww.stride) {
+    for (WaveWalk ww(total, a.xcd_walk); ww.t < ww.end; ww.t += ww.stride) {
         const int t = ww.t;
         if (t < seg_t0 || t >= seg_t1) {
             seg = find_segment(a.tile_prefix, a.nseg, t);
@@ -1008,13 +1008,13 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs h) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_moments_particles(MomArgs m) {
     __shared__ double sK[4];
-    const int total = m.tile_prefix[m.nseg];
+    // only the tiles of the requested line's four segments
+    const int t_first = m.tile_prefix[4 * m.line], t_last = m.tile_prefix[4 * m.line + 4];
     double kin = 0.0;
-    for (TileWalk tw(total); tw.t < tw.end; tw.t += tw.stride) {
-        const int t = tw.t;
+    for (TileWalk tw(t_last - t_first); tw.t < tw.end; tw.t += tw.stride) {
+        const int t = t_first + tw.t;
         const int seg = find_segment(m.tile_prefix, m.nseg, t);
         const int line = seg >> 2, sp = seg & 3;
-        if (line != m.line) continue;
         const LineDev& L = m.lines[line];
         const int ncur = m.n_cur[seg];
         const int64_t base = m.seg_base[seg];

@@ -66,6 +66,12 @@ class CProfile(ctypes.Structure):
 KERNELS = ("push", "atmosphere", "field", "plan", "sort", "convert")
 
 
+class CTuneOut(ctypes.Structure):
+    _fields_ = [("push_blocks_per_cu", ctypes.c_int32), ("xcd_walk", ctypes.c_int32), ("sort_interval", ctypes.c_int32),
+                ("n_trials", ctypes.c_int32), ("ms_per_step_before", ctypes.c_double),
+                ("ms_per_step_after", ctypes.c_double)]
+
+
 class CMlpTrainConfig(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("n_samples", ctypes.c_int64), ("batch", ctypes.c_int32),
                 ("steps", ctypes.c_int32), ("lr", ctypes.c_double), ("lr_final", ctypes.c_double),
@@ -96,6 +102,8 @@ _SIGS = {
     "pic1d_rics_eval": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int64, P, P, P, P, P]),
     "pic1d_profile": (ctypes.c_int, [P, ctypes.c_int32]),
     "pic1d_profile_read": (ctypes.c_int, [P, ctypes.POINTER(CProfile)]),
+    "pic1d_set_graph": (ctypes.c_int, [P, ctypes.c_int32]),
+    "pic1d_autotune": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(CTuneOut)]),
     "pic1d_mlp_param_count": (ctypes.c_int, []),
     "pic1d_mlp_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "pic1d_mlp_samples": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, P, P, P]),
@@ -294,6 +302,16 @@ class Pic1D:
 
     def set_step(self, step):
         self._check(self.lib.pic1d_set_step(self.h, int(step)))
+
+    def set_graph(self, steps_per_graph):
+        """Replay the step sequence from captured HIP graphs of this many steps (0: eager)."""
+        self._check(self.lib.pic1d_set_graph(self.h, int(steps_per_graph)))
+
+    def autotune(self, trial_steps=5):
+        """Pick the launch shape by timing real steps; returns the choice and the timings."""
+        out = CTuneOut()
+        self._check(self.lib.pic1d_autotune(self.h, int(trial_steps), ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in CTuneOut._fields_}
 
     def rics_eval(self, line, s_cells, u):
         """F_hat, Ndot_hat, eps of the configured backend at device tensors s_cells, u (float32)."""

@@ -19,7 +19,13 @@ at the sizes of the benchmark configurations:
             n_max = 3 n0 per cell (at this resolution almost every lepton with
             gamma >~ 1e3 in the b >= 0.1 region scatters each step, and the
             cascade is held by n_max).
+* cfg3()    the batched path: 256 lines with R_max log-uniform in [2, 100]
+            (seeded draw), 1,024 to 32,768 cells per line (a power law in
+            R_max through those endpoints, rounded to multiples of 256),
+            32-256 e-/e+ per cell per line (uniform integers), cold start,
+            TABLE RICS, pairs on with curvature conversion.
 """
+import numpy as np
 
 CFG1 = dict(
     rics="table", table_nlg=256, table_ns=512, kT_keV=0.5, j_twist=0.5, ppc0=64.0, pairs=False,
@@ -46,6 +52,21 @@ CFG4 = dict(
     lines=[dict(r_eq=4.0, n_cells=65536, ppc_init=200, init="hot", init_gamma_max=1.0e4,
                 capacity=[40_000_000, 40_000_000, 0, 0])],
 )
+
+
+def cfg3(n_lines=256, seed=0, rics="table", headroom=1.05):
+    """The batched many-line workload (about 2.3e6 cells and 6.6e8 particles at 256 lines)."""
+    rng = np.random.default_rng(seed)
+    R = 2.0 * 50.0 ** rng.random(n_lines)
+    expo = np.log(32.0) / np.log(50.0)                   # 1,024 cells at R_max = 2, 32,768 at 100
+    cells = np.clip(np.round(1024.0 * (R / 2.0) ** expo / 256.0) * 256.0, 1024, 32768).astype(int)
+    ppc = rng.integers(32, 257, n_lines)
+    lines = []
+    for r, n, p in zip(R, cells, ppc):
+        cap = int(headroom * p * n) + 4096
+        lines.append(dict(r_eq=float(r), n_cells=int(n), ppc_init=int(p), init="cold", capacity=[cap, cap, 0, 0]))
+    return dict(rics=rics, table_nlg=256, table_ns=512, kT_keV=0.5, j_twist=0.5, ppc0=float(np.mean(ppc)),
+                pairs=True, conversion="curvature", seed=seed, sort_interval=50, lines=lines)
 
 
 def small(r_eq=4.0, n_cells=96, ppc=16, init="hot", **kw):

@@ -1,0 +1,138 @@
+"""The batched path: many ragged lines in one state, HIP-graph replay and the autotuner."""
+import numpy as np
+import pytest
+
+from paper_2609_17661_amd import Pic1D, workloads
+
+from . import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _ragged(n_lines=6, seed=3, **kw):
+    """Lines of uneven length and particle count, hot plasma, pairs and atmosphere."""
+    rng = np.random.default_rng(seed)
+    lines = []
+    for i in range(n_lines):
+        n = int(rng.integers(40, 200))
+        p = int(rng.integers(3, 14))
+        lines.append(dict(r_eq=float(2.0 * 15.0 ** rng.random()), n_cells=n, ppc_init=p, init="hot",
+                          init_gamma_max=2e3, capacity=[200_000, 200_000, 40_000, 40_000]))
+    cfg = dict(rics="exact", kT_keV=0.5, j_twist=0.5, ppc0=8.0, seed=seed, pairs=True, conversion="curvature",
+               atmosphere=True, sort_interval=3, lines=lines)
+    cfg.update(kw)
+    return cfg
+
+
+def _state(sim):
+    """Every line's particles sorted by id, E, counts and counters."""
+    out = []
+    for li in range(sim.n_lines):
+        parts = []
+        for s in range(4):
+            p = sim.get_particles(li, s)
+            o = np.argsort(p["id"])
+            parts.append({k: v[o] for k, v in p.items()})
+        m = sim.moments(li)
+        out.append(dict(parts=parts, E=sim.get_field(li), count=m["count"], counters=m["counters"], step=m["step"]))
+    return out
+
+
+def _assert_same(a, b):
+    for la, lb in zip(a, b):
+        assert la["step"] == lb["step"]
+        assert la["count"] == lb["count"]
+        assert la["counters"] == lb["counters"]
+        assert np.array_equal(la["E"], lb["E"])
+        for pa, pb in zip(la["parts"], lb["parts"]):
+            for k in pa:
+                assert np.array_equal(pa[k], pb[k]), k
+
+
+def test_ragged_lines_step_parity():
+    cfg = _ragged()
+    ocfg = parity.oracle_config(cfg)
+    sim = Pic1D(cfg)
+    _print("ragged lines", [(l["r_eq"], l["n_cells"], l["ppc_init"]) for l in cfg["lines"]])
+    for k in range(3):
+        before = parity.snapshot(sim)
+        sim.step(1)
+        after = parity.snapshot(sim)
+        rep, _ = parity.compare_step(ocfg, before, after)
+        _print(f"  step {k}: {rep}")
+        assert rep["excused"] <= max(3, 1e-3 * rep["compared"])
+        sim.step(2)
+    for li in range(sim.n_lines):
+        assert sim.moments(li)["gauss_residual"] <= 1e-6
+
+
+def test_graph_replay_equals_eager_stepping():
+    cfg = _ragged(seed=5)
+    eager = Pic1D(cfg)
+    graph = Pic1D(cfg)
+    graph.set_graph(6)               # 6 steps per graph: two sorts (interval 3) per replay
+    done = 0
+    # calls that start off the graph boundary, span several replays and end inside one;
+    # eager moments, particle reads and synchronisations between the replays
+    for n in (4, 7, 12, 1, 13):
+        eager.step(n)
+        graph.step(n)
+        done += n
+        _print("steps", done)
+        _assert_same(_state(eager), _state(graph))
+
+
+def test_graph_replay_without_sorting():
+    cfg = _ragged(seed=6, sort_interval=0, pairs=False)
+    eager = Pic1D(cfg)
+    graph = Pic1D(cfg)
+    graph.set_graph(5)
+    for n in (5, 10, 3):
+        eager.step(n)
+        graph.step(n)
+        _assert_same(_state(eager), _state(graph))
+
+
+def test_autotune_changes_speed_not_results():
+    cfg = _ragged(seed=7)
+    ref = Pic1D(cfg)
+    tuned = Pic1D(cfg)
+    out = tuned.autotune(trial_steps=4)
+    _print("autotune", out)
+    assert out["n_trials"] >= 3
+    assert out["push_blocks_per_cu"] in (1, 2, 3, 4, 6, 8)
+    assert out["ms_per_step_after"] <= out["ms_per_step_before"]
+    steps = tuned.moments(0)["step"]
+    ref.step(steps)
+    _assert_same(_state(ref), _state(tuned))
+    tuned.set_graph(out["sort_interval"])
+    tuned.step(2 * out["sort_interval"] + 1)
+    ref.step(2 * out["sort_interval"] + 1)
+    _assert_same(_state(ref), _state(tuned))
+
+
+def test_many_lines_conserve_charge_per_line():
+    """64 lines of the batched workload's shape (scaled down): Gauss per line after graph replays."""
+    cfg = workloads.cfg3(n_lines=64, seed=1)
+    for ln in cfg["lines"]:
+        ln["n_cells"] = max(256, ln["n_cells"] // 16)
+        ln["ppc_init"] = max(4, ln["ppc_init"] // 8)
+        ln["capacity"] = [ln["n_cells"] * ln["ppc_init"] * 2, ln["n_cells"] * ln["ppc_init"] * 2, 0, 0]
+    cfg["lines"] = [dict(l, init="hot", init_gamma_max=1e3) for l in cfg["lines"]]
+    cfg["ppc0"] = 16.0
+    cfg["sort_interval"] = 10
+    cfg["pairs"] = False          # a hot plasma on these lines cascades past any fixed capacity
+    sim = Pic1D(cfg)
+    sim.set_graph(20)
+    sim.step(45)
+    worst = 0.0
+    for li in range(sim.n_lines):
+        m = sim.moments(li)
+        worst = max(worst, m["gauss_residual"])
+        assert m["step"] == 45
+    _print("64 lines: worst Gauss residual", worst)
+    assert worst <= 1e-6
