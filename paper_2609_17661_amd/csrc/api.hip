@@ -67,6 +67,7 @@ struct pic1d_state {
     int32_t *seg_cap = nullptr, *n_cur = nullptr, *alloc = nullptr, *tile_prefix = nullptr, *new_count = nullptr;
     LineDev* dlines = nullptr;
     double *E = nullptr, *j_last = nullptr, *E_sum = nullptr, *j_sum = nullptr;
+    float* E32 = nullptr;
     unsigned long long* J = nullptr;
     int32_t* hist[2] = {nullptr, nullptr};
     int32_t *pair_step = nullptr, *pair_last = nullptr, *cursor = nullptr, *cell_line = nullptr;
@@ -188,6 +189,7 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->tile_prefix = cv.take<int32_t>(L.nseg + 1);
     s->dlines = cv.take<LineDev>(L.n_lines);
     s->E = cv.take<double>(L.n_cells);
+    s->E32 = cv.take<float>(L.n_cells);
     s->J = cv.take<unsigned long long>(L.n_cells);
     s->j_last = cv.take<double>(L.n_cells);
     s->E_sum = cv.take<double>(L.n_cells);
@@ -228,7 +230,7 @@ PushArgs push_args(pic1d_state* st) {
     a.nlg = st->cfg.table_nlg; a.ns = st->cfg.table_ns;
     a.pairs = st->cfg.pairs; a.conversion = st->cfg.conversion;
     a.gravity = st->cfg.atmosphere && st->cfg.gravity;
-    a.lines = st->dlines; a.E = st->E; a.J = st->J; a.nodes = st->nodes; a.rc_nodes = st->rc_nodes;
+    a.lines = st->dlines; a.E32 = st->E32; a.J = st->J; a.nodes = st->nodes; a.rc_nodes = st->rc_nodes;
     a.table = st->table; a.hist[0] = st->hist[0]; a.hist[1] = st->hist[1];
     a.pair_step = st->pair_step; a.counters = st->counters; a.sc = st->sc;
     a.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); a.key1 = (uint32_t)(st->cfg.seed >> 32);
@@ -545,7 +547,7 @@ int enqueue_step(pic1d_state* st) {
             hipLaunchKernelGGL(k_atmosphere, dim3(std::max(blocks, 1)), dim3(256), 0, st->stream, a);
             prof_end(st, pk);
         }
-        f.E = st->E; f.J = st->J; f.j_last = st->j_last; f.hist[0] = st->hist[0]; f.hist[1] = st->hist[1];
+        f.E = st->E; f.E32 = st->E32; f.J = st->J; f.j_last = st->j_last; f.hist[0] = st->hist[0]; f.hist[1] = st->hist[1];
         f.pair_step = st->pair_step; f.pair_last = st->pair_last; f.E_sum = st->E_sum; f.j_sum = st->j_sum;
         f.pair_sum = st->pair_sum; f.n_sum = st->n_sum; f.avg_count = st->avg_count; f.cell_line = st->cell_line;
         f.lines = st->dlines; f.n_total = nt; f.frozen = st->cfg.frozen_field; f.avg_start = st->cfg.avg_start_step;
@@ -914,6 +916,8 @@ int pic1d_set_field(pic1d_state* st, int32_t line, const double* E) {
         if (!isfinite(E[i])) return fail(st, PIC1D_EINVAL, "non-finite field value");
     HIP_TRY(st, hipStreamSynchronize(st->stream));
     HIP_TRY(st, copy_sync(st->stream, st->E + d.cell_base, E, 8 * (size_t)d.n_cells, hipMemcpyHostToDevice));
+    std::vector<float> e32(E, E + d.n_cells);
+    HIP_TRY(st, copy_sync(st->stream, st->E32 + d.cell_base, e32.data(), 4 * (size_t)d.n_cells, hipMemcpyHostToDevice));
     return PIC1D_OK;
 }
 

@@ -43,7 +43,7 @@ struct PushArgs {
     int32_t nlg, ns;
     int32_t pairs, conversion, gravity;
     const LineDev* lines;
-    const double* E;
+    const float* E32;          // float32 copy of E (the gather needs no more)
     unsigned long long* J;
     const float4* nodes;
     const double* rc_nodes;
@@ -119,6 +119,7 @@ struct BookArgs {
 
 struct FieldArgs {
     double* E;
+    float* E32;
     unsigned long long* J;
     double* j_last;
     int32_t* hist[2];

@@ -341,14 +341,14 @@ __device__ __forceinline__ float mlp_drag_half(const PushArgs& a, const bf16x8* 
 // beyond the outermost cell centres.
 struct CellCache {
     int cell;
-    double Em, E0, Ep;      // E at the centres of cells c-1, c, c+1
+    float Em, E0, Ep;       // E at the centres of cells c-1, c, c+1
     float4 n0, n1;          // geometry nodes c, c+1
 };
 
 template <bool GEO>
 __device__ __forceinline__ void cache_load(CellCache& cc, const PushArgs& a, const LineDev& L, int c0) {
     cc.cell = c0;
-    const double* E = a.E + L.cell_base;
+    const float* E = a.E32 + L.cell_base;
     cc.Em = E[max(c0 - 1, 0)];
     cc.E0 = E[c0];
     cc.Ep = E[min(c0 + 1, L.n_cells - 1)];
@@ -360,24 +360,25 @@ __device__ __forceinline__ void cache_load(CellCache& cc, const PushArgs& a, con
 
 // Everything one particle does in one step: gather, RICS, kick, move, and the
 // deposit of its path in fixed point.  Written without data-dependent branches on
-// the common path (dead lanes compute on sanitised inputs and are masked out).
-// Returns the new cell (DEAD_CELL when absorbed) in c1; da goes to the old cell,
-// db to the neighbour the path crossed into (d = c1 - c0 in {-1, 0, 1}).
+// the common path (dead lanes compute on sanitised inputs and deposit nothing).
+// Returns the new cell (DEAD_CELL when absorbed) in c1, d = c1 - c0 in {-1, 0, 1},
+// and the path's overlaps with cells c0-1, c0, c0+1 in units of 2^-28 cell
+// (unsigned by the charge; jm and jp vanish unless the path leaves the cell).
 template <int BACKEND>
 __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDev& L, const TileCtx& T,
                                                  const CellCache& cc, bool alive, int line, int sp, int64_t k,
                                                  int c0, float o0, float& u, Counts& cnt, int& c1, float& o1,
-                                                 long long& da, long long& db, int& d, const bf16x8* W,
+                                                 int& jm, int& j0, int& jp, int& d, const bf16x8* W,
                                                  const float* Wb) {
     const int n = L.n_cells;
     constexpr bool RICS = BACKEND != RICS_OFF;
 
     // field gather: E at x^n, linear between cell centres
     const bool upper = o0 >= 0.5f;
-    const double Ea = upper ? cc.E0 : cc.Em;
-    const double Eb = upper ? cc.Ep : cc.E0;
+    const float Ea = upper ? cc.E0 : cc.Em;
+    const float Eb = upper ? cc.Ep : cc.E0;
     const float w = upper ? o0 - 0.5f : o0 + 0.5f;
-    float kick = T.qm * (float)fma((double)w, Eb - Ea, Ea) * L.invC;
+    float kick = T.qm * fmaf(w, Eb - Ea, Ea) * L.invC;
     const double x = (double)c0 + (double)o0;
     if (T.gravity) {
         const double dw = fmin(x, (double)n - x);
@@ -426,15 +427,18 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
     o1 = fix ? 0.0f : o1;
     d = up - dn + fix;
     c1 = c0 + d;
-    // fixed-point deposit (units of 2^-32 cell) of the path, from the stored old and new
-    // offsets quantised to that grid: differences of quantised positions telescope,
-    // so the deposit equals the change of the quantised charge density exactly
-    const long long f0 = (long long)__float2uint_rn(o0 * 4294967296.0f);
-    const long long f1 = (long long)__float2uint_rn(o1 * 4294967296.0f);
-    da = (d == 0) ? f1 - f0 : ((d > 0) ? 4294967296ll - f0 : -f0);
-    db = (d > 0) ? f1 : ((d < 0) ? f1 - 4294967296ll : 0ll);
-    if (c1 < 0 || c1 >= n) db = 0;            // the part of the path beyond a wall is not deposited
-    if (T.negative) { da = -da; db = -db; }
+    // fixed-point deposit of the path from the stored old and new offsets quantised
+    // to 2^-28 cell: X1 is the new position relative to the old cell's left face.
+    // Differences of quantised stored positions telescope, so the deposit equals the
+    // change of the quantised charge density exactly.  The parts beyond a wall land
+    // in cells -1 or n, which the flush drops.
+    constexpr int ONE = 1 << POS_BITS;
+    const int f0 = (int)(o0 * POS_SCALE);
+    int X1 = d * ONE + (int)(o1 * POS_SCALE);
+    X1 = alive ? X1 : f0;
+    jm = min(X1, 0);
+    j0 = min(max(X1, 0), ONE) - f0;
+    jp = max(X1 - ONE, 0);
     const bool gone = c1 < 0 || c1 >= n;
     cnt.absorbed += (alive && gone) ? 1 : 0;
     c1 = gone ? DEAD_CELL : c1;
@@ -469,10 +473,14 @@ __device__ __forceinline__ void wave_sync() {
 // fixed-point current with one atomic per touched cell.  No block-level
 // synchronisation.
 template <int BACKEND>
-__global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB) void k_push(PushArgs a) {
+__global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB)
+__attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(PushArgs a) {
     constexpr int TPB = BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB;
     __shared__ unsigned long long sJ[TPB / 64][WW];
     __shared__ int sH[TPB / 64][WW];
+    __shared__ int sPc[TPB / 64][PUSH_PPT][64];      // the wave's tile: cell, offset, momentum
+    __shared__ float sPo[TPB / 64][PUSH_PPT][64];
+    __shared__ float sPu[TPB / 64][PUSH_PPT][64];
     // surrogate weights, staged once per block (the network runs on them for every particle)
     __shared__ bf16x8 sW[BACKEND == RICS_MLP ? FT_TOTAL * 64 : 1];
     __shared__ float sWb[BACKEND == RICS_MLP ? MLP_BIAS : 1];
@@ -509,11 +517,11 @@ __global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB) void
         const int ncur = a.n_cur[seg];
         const int64_t base = a.seg_base[seg];
         // this lane's PUSH_PPT consecutive particles (vector loads; slots up to the
-        // capacity, a multiple of 256, always exist)
+        // capacity, a multiple of 256, always exist), staged in the wave's LDS slots
+        // [q][lane] so the particle loop indexes them freely without bank conflicts
         const int ib = (t - seg_t0) * PUSH_TILE + lane * PUSH_PPT;
         const int nv = max(0, min(PUSH_PPT, ncur - ib));
-        int c[PUSH_PPT];
-        float o[PUSH_PPT], uu[PUSH_PPT];
+        int lo = INT32_MAX, hi = INT32_MIN, first = -1;
         {
             const int4* cp = reinterpret_cast<const int4*>(a.cell + base + ib);
             const float4* op = reinterpret_cast<const float4*>(a.off + base + ib);
@@ -523,19 +531,21 @@ __global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB) void
                 int4 ci = make_int4(DEAD_CELL, DEAD_CELL, DEAD_CELL, DEAD_CELL);
                 float4 oi = make_float4(0.5f, 0.5f, 0.5f, 0.5f), ui = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (nv > 0) { ci = cp[h]; oi = op[h]; ui = up[h]; }
-                c[4 * h + 0] = ci.x; c[4 * h + 1] = ci.y; c[4 * h + 2] = ci.z; c[4 * h + 3] = ci.w;
-                o[4 * h + 0] = oi.x; o[4 * h + 1] = oi.y; o[4 * h + 2] = oi.z; o[4 * h + 3] = oi.w;
-                uu[4 * h + 0] = ui.x; uu[4 * h + 1] = ui.y; uu[4 * h + 2] = ui.z; uu[4 * h + 3] = ui.w;
-            }
-        }
-        int lo = INT32_MAX, hi = INT32_MIN, first = -1;
+                const int cv[4] = {ci.x, ci.y, ci.z, ci.w};
+                const float ov[4] = {oi.x, oi.y, oi.z, oi.w}, uv[4] = {ui.x, ui.y, ui.z, ui.w};
 #pragma unroll
-        for (int q = PUSH_PPT - 1; q >= 0; --q) {
-            if (q >= nv) c[q] = DEAD_CELL;
-            if (c[q] != DEAD_CELL) {
-                lo = min(lo, c[q] - 1);
-                hi = max(hi, c[q] + 1);
-                first = c[q];
+                for (int i = 0; i < 4; ++i) {
+                    const int q = 4 * h + i;
+                    const int c = q < nv ? cv[i] : DEAD_CELL;
+                    if (c != DEAD_CELL) {
+                        lo = min(lo, c - 1);
+                        hi = max(hi, c + 1);
+                        if (first < 0) first = c;
+                    }
+                    sPc[wid][q][lane] = c;
+                    sPo[wid][q][lane] = ov[i];
+                    sPu[wid][q][lane] = uv[i];
+                }
             }
         }
         // window [lo, hi] of cells this wavefront's deposit can touch
@@ -566,67 +576,55 @@ __global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB) void
 
         CellCache cc;
         cache_load<GEO>(cc, a, L, first >= 0 ? first : 0);
-        // per-lane run accumulator: deposit and new-cell counts of cells key-1, key, key+1
+        // per-lane run accumulator over consecutive particles of one cell: deposits
+        // (2^-28 cell) into cells key-1, key, key+1 and the new-cell counts of the same
+        // three cells packed in 10-bit fields of hc
         int key = cc.cell;
-        long long jv0 = 0, jv1 = 0, jv2 = 0;
-        int hc0 = 0, hc1 = 0, hc2 = 0;
+        int jv0 = 0, jv1 = 0, jv2 = 0, hc = 0;
         auto flush_run = [&]() {
-            const long long jv[3] = {jv0, jv1, jv2};
-            const int hv[3] = {hc0, hc1, hc2};
+            const int jv[3] = {jv0, jv1, jv2};
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const int cell = key - 1 + r;
+                const int hv = (hc >> (10 * r)) & 1023;
                 if (cell >= 0 && cell < L.n_cells) {
+                    const long long j = (long long)(T.negative ? -jv[r] : jv[r]) << POS_TO_FIX;
                     if (use_lds) {
-                        if (jv[r] != 0) atomicAdd(&sJ[wid][cell - lo], (unsigned long long)jv[r]);
-                        if (hv[r] != 0) atomicAdd(&sH[wid][cell - lo], hv[r]);
+                        if (j != 0) atomicAdd(&sJ[wid][cell - lo], (unsigned long long)j);
+                        if (hv != 0) atomicAdd(&sH[wid][cell - lo], hv);
                     } else {
-                        if (jv[r] != 0) atomicAdd(&Jg[cell], (unsigned long long)jv[r]);
-                        if (hv[r] != 0) atomicAdd(&Hg[4 * (size_t)cell], hv[r]);
+                        if (j != 0) atomicAdd(&Jg[cell], (unsigned long long)j);
+                        if (hv != 0) atomicAdd(&Hg[4 * (size_t)cell], hv);
                     }
                 }
             }
-            jv0 = jv1 = jv2 = 0;
-            hc0 = hc1 = hc2 = 0;
+            jv0 = jv1 = jv2 = hc = 0;
         };
-        // the particle in slot 0 is advanced and its result rotated in at the end, so
-        // the register arrays are only ever indexed by constants
 #pragma unroll 1
         for (int q = 0; q < PUSH_PPT; ++q) {
-            const int c0 = c[0];
+            const int c0 = sPc[wid][q][lane];
             const bool alive = c0 != DEAD_CELL;
             if (alive && c0 != cc.cell) {
                 flush_run();
                 cache_load<GEO>(cc, a, L, c0);
                 key = c0;
             }
-            float uq = alive ? uu[0] : 0.0f;
-            const float oq = alive ? o[0] : 0.5f;
-            int c1, d;
+            const float u0 = sPu[wid][q][lane];
+            const float o0 = sPo[wid][q][lane];
+            float uq = alive ? u0 : 0.0f;
+            const float oq = alive ? o0 : 0.5f;
+            int c1, d, jm, j0, jp;
             float o1;
-            long long da, db;
             advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + q, cc.cell, oq, uq, cnt, c1, o1,
-                                      da, db, d, sW, sWb);
+                                      jm, j0, jp, d, sW, sWb);
             cnt.pushed += alive ? 1 : 0;
-            jv1 += alive ? da : 0ll;
-            jv0 += (alive && d < 0) ? db : 0ll;
-            jv2 += (alive && d > 0) ? db : 0ll;
-            const bool kept = alive && c1 != DEAD_CELL;
-            hc0 += (kept && d < 0) ? 1 : 0;
-            hc1 += (kept && d == 0) ? 1 : 0;
-            hc2 += (kept && d > 0) ? 1 : 0;
-            const int cq = alive ? c1 : DEAD_CELL;
-            const float oo = kept ? o1 : o[0];
-            const float un = alive ? uq : uu[0];
-#pragma unroll
-            for (int r = 0; r < PUSH_PPT - 1; ++r) {
-                c[r] = c[r + 1];
-                o[r] = o[r + 1];
-                uu[r] = uu[r + 1];
-            }
-            c[PUSH_PPT - 1] = cq;
-            o[PUSH_PPT - 1] = oo;
-            uu[PUSH_PPT - 1] = un;
+            jv0 += jm;
+            jv1 += j0;
+            jv2 += jp;
+            hc += alive ? (1 << (10 * (d + 1))) : 0;
+            sPc[wid][q][lane] = alive ? c1 : DEAD_CELL;
+            sPo[wid][q][lane] = (alive && c1 != DEAD_CELL) ? o1 : o0;
+            sPu[wid][q][lane] = alive ? uq : u0;
         }
         flush_run();
         // write back (vector stores for full groups; never touch slots >= ncur, where
@@ -637,17 +635,20 @@ __global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB) void
             float4* up = reinterpret_cast<float4*>(a.u + base + ib);
 #pragma unroll
             for (int h = 0; h < PUSH_PPT / 4; ++h) {
-                cp[h] = make_int4(c[4 * h], c[4 * h + 1], c[4 * h + 2], c[4 * h + 3]);
-                op[h] = make_float4(o[4 * h], o[4 * h + 1], o[4 * h + 2], o[4 * h + 3]);
-                up[h] = make_float4(uu[4 * h], uu[4 * h + 1], uu[4 * h + 2], uu[4 * h + 3]);
+                cp[h] = make_int4(sPc[wid][4 * h][lane], sPc[wid][4 * h + 1][lane], sPc[wid][4 * h + 2][lane],
+                                  sPc[wid][4 * h + 3][lane]);
+                op[h] = make_float4(sPo[wid][4 * h][lane], sPo[wid][4 * h + 1][lane], sPo[wid][4 * h + 2][lane],
+                                    sPo[wid][4 * h + 3][lane]);
+                up[h] = make_float4(sPu[wid][4 * h][lane], sPu[wid][4 * h + 1][lane], sPu[wid][4 * h + 2][lane],
+                                    sPu[wid][4 * h + 3][lane]);
             }
         } else {
 #pragma unroll
             for (int q = 0; q < PUSH_PPT; ++q) {
                 if (q < nv) {
-                    a.cell[base + ib + q] = c[q];
-                    a.off[base + ib + q] = o[q];
-                    a.u[base + ib + q] = uu[q];
+                    a.cell[base + ib + q] = sPc[wid][q][lane];
+                    a.off[base + ib + q] = sPo[wid][q][lane];
+                    a.u[base + ib + q] = sPu[wid][q][lane];
                 }
             }
         }
@@ -853,7 +854,11 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f) {
         const double j = (double)J * FIX_INV * L.Q;
         f.J[g] = 0ull;
         f.j_last[g] = j;
-        if (!f.frozen) f.E[g] -= 4.0 * 3.14159265358979323846 * (j - L.j_tw);
+        if (!f.frozen) {
+            const double En = f.E[g] - 4.0 * 3.14159265358979323846 * (j - L.j_tw);
+            f.E[g] = En;
+            f.E32[g] = (float)En;
+        }
         const int ps = f.pair_step[g];
         f.pair_step[g] = 0;
         if (averaging) {
@@ -1026,8 +1031,8 @@ __global__ __launch_bounds__(256) void k_moments_particles(MomArgs m) {
             if (i >= ncur) continue;
             const int c = m.cell[base + i];
             if (c == DEAD_CELL) continue;
-            // cloud-in-cell weights of the position quantised to 2^-32 cell, as in the deposit
-            const long long f = (long long)__float2uint_rn(m.off[base + i] * 4294967296.0f);
+            // cloud-in-cell weights of the position quantised as in the deposit (2^-28 cell)
+            const long long f = (long long)(int)(m.off[base + i] * POS_SCALE) << POS_TO_FIX;
             const long long sg = (qs < 0.0) ? -1 : 1;
             const double u = (double)m.u[base + i];
             atomicAdd(&m.rho[c], (unsigned long long)(sg * (4294967296ll - f)));

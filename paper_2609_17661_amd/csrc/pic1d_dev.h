@@ -24,6 +24,12 @@ constexpr int NSPEC = 4;
 constexpr int NCOUNT = 16;                        // counters per line
 constexpr double FIX_SCALE = 4294967296.0;        // 2^32: fixed point of the current deposit
 constexpr double FIX_INV = 1.0 / 4294967296.0;
+// Positions enter the deposit and the charge density quantised to 2^-28 cell
+// (exact for offsets >= 1/16, where float32 spacing is at least that); one
+// quantum is 2^4 fixed-point units of the current.
+constexpr int POS_BITS = 28;
+constexpr float POS_SCALE = 268435456.0f;          // 2^28
+constexpr int POS_TO_FIX = 4;                      // 2^(32 - POS_BITS) as a shift
 constexpr float Y_CUT = 80.0f;                    // Planck factors vanish beyond y = 80
 
 // Philox stream tags (fourth counter word of each draw).
