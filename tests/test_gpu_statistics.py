@@ -1,0 +1,87 @@
+"""Long-run statistics of the HIP path against the oracle.
+
+Float32 and float64 trajectories separate over time, so long runs are compared
+statistically:
+  * time-averaged profiles of the species densities, the current and E on the
+    R_max = 4 line (512 cells, 64 e-/e+ per cell) over steps 200-999, within
+    2% in the relative L2 norm ||<f>_gpu - <f>_oracle||_2 / max(||<f>_oracle||_2,
+    floor), with floors sqrt(N) n0 for the densities, |j_psi| sqrt(N) for the
+    current and 4 pi Q ppc0 d0 sqrt(N) for E (one n0 of charge over a skin depth);
+  * pair yields of the hot line over several steps, within 3 sigma (Poisson).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pic
+from paper_2609_17661_amd import Pic1D, workloads
+
+from . import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _rel_l2(a, b, floor):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), floor))
+
+
+def test_time_averaged_profiles_match_oracle():
+    steps, avg_start = 1000, 200
+    cfg = dict(workloads.CFG1, avg_start_step=avg_start)
+    sim = Pic1D(cfg)
+    sim.step(steps)
+    m = sim.moments(0, average=True)
+    assert m["avg_steps"] == steps - avg_start
+
+    ocfg = parity.oracle_config(cfg)
+    st = pic.init_state(ocfg)
+    ln = st.lines[0]
+    n = ln.n
+    ppc0 = ocfg["ppc0"]
+    sums = dict(n=np.zeros((4, n)), j=np.zeros(n), E=np.zeros(n))
+    for k in range(steps):
+        pic.step(st)
+        if k >= avg_start:
+            for s in range(4):
+                x = st.parts[0][s]["x"]
+                if x.size:
+                    sums["n"][s] += np.bincount(np.floor(x).astype(np.int64), minlength=n)
+            sums["j"] += st.j_last[0]
+            sums["E"] += st.E[0]
+        if k % 200 == 0:
+            _print("oracle step", k)
+    navg = steps - avg_start
+    n_o = sums["n"] / navg / ppc0
+    j_o = sums["j"] / navg / (ppc0 * ln.Q * ln.C)
+    E_o = sums["E"] / navg
+    rn = [_rel_l2(m["n"][s], n_o[s], math.sqrt(n)) for s in (0, 1)]
+    rj = _rel_l2(m["j"], j_o, abs(ocfg["j_twist"]) * math.sqrt(n))
+    rE = _rel_l2(m["E"], E_o, 4 * math.pi * ln.Q * ppc0 * ocfg["d0_cells"] * math.sqrt(n))
+    _print("relative L2: n_e", rn[0], "n_p", rn[1], "j", rj, "E", rE)
+    assert max(rn) <= 0.02 and rj <= 0.02 and rE <= 0.02
+
+
+def test_pair_yield_matches_oracle_within_three_sigma():
+    # the hot line cascades (every lepton with gamma >~ 10 scatters each step at this
+    # resolution); n_max = 3 n0 per cell caps it at ~1e5 particles
+    cfg = dict(workloads.CFG1_HOT, nmax_over_n0=3.0)
+    sim = Pic1D(cfg)
+    ocfg = parity.oracle_config(cfg)
+    st = pic.init_state(ocfg)
+    steps = 8
+    sim.step(steps)
+    for _ in range(steps):
+        pic.step(st)
+    g = sim.moments(0)["counters"]["pairs_created"]
+    o = st.counters[0]["pairs_created"]
+    e_g = sim.moments(0)["counters"]["events"]
+    e_o = st.counters[0]["events"]
+    _print("pairs gpu", g, "oracle", o, "events gpu", e_g, "oracle", e_o)
+    assert o > 100
+    assert abs(g - o) <= 3.0 * math.sqrt(o)
+    assert abs(e_g - e_o) <= 3.0 * math.sqrt(e_o)
