@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only the surrogate comparison (for profiling its kernels)")
     ap.add_argument("--surrogate-steps", type=int, default=10)
     ap.add_argument("--mlp-train-steps", type=int, default=50000)
     ap.add_argument("--copy-calibration", action="store_true")
@@ -295,6 +297,10 @@ def main():
 
     from paper_2609_17661_amd import Pic1D, workloads
 
+    if args.surrogate_only:
+        print(json.dumps({"surrogate_vs_table": surrogate_comparison(args.surrogate_steps, 3, args.mlp_train_steps)}),
+              flush=True)
+        return
     cfg = dict(workloads.CFG2 if args.workload == "cfg2" else workloads.CFG1)
     cfg["rics"] = args.backend
     sim = Pic1D(cfg, device="cuda:0")

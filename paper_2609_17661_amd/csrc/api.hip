@@ -528,7 +528,7 @@ int enqueue_step(pic1d_state* st) {
             ca.conversion = st->cfg.conversion;
             ca.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); ca.key1 = (uint32_t)(st->cfg.seed >> 32);
             const int pk = prof_begin(st, 5);
-            hipLaunchKernelGGL(k_convert, dim3(PHOTON_REPL), dim3(256), 0, st->stream, ca);
+            hipLaunchKernelGGL(k_convert, dim3(st->aux_blocks), dim3(256), 0, st->stream, ca);
             prof_end(st, pk);
         }
         if (st->cfg.atmosphere && st->lay.n_layer > 0) {

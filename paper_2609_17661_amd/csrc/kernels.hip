@@ -678,58 +678,92 @@ template __global__ void k_push<RICS_MLP>(PushArgs);
 // is below n_max.  Float64 throughout: the member momenta are ill-conditioned in
 // eps when eps/2 is close to 1.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool append_slot(const ConvertArgs& a, int seg, int cell, float off, float u, uint64_t id) {
-    const int slot = atomicAdd(&a.alloc[seg], 1);
-    if (slot >= a.seg_cap[seg]) {
-        set_error(&a.sc->err, -3);
-        return false;
-    }
-    const int64_t k = a.seg_base[seg] + slot;
-    a.cell[k] = cell;
-    a.off[k] = off;
-    a.u[k] = u;
-    a.id[k] = id;
-    return true;
-}
-
+// The whole grid walks the photon records of all regions, one wavefront per 64
+// consecutive records.  Appends and counters are aggregated per wavefront and
+// line: one atomic per (wave, line) on each allocation counter and counter slot.
 __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
     if (a.sc->err != 0) return;
     const uint64_t step = a.sc->step;
     const int32_t* hist_in = (step & 1) ? a.hist[1] : a.hist[0];
     int32_t* hist_out = (step & 1) ? a.hist[0] : a.hist[1];
-    for (int r = blockIdx.x; r < PHOTON_REPL; r += gridDim.x) {
-        const int np = min(a.n_photons[r], a.photon_region);
-        for (int i = threadIdx.x; i < np; i += blockDim.x) {
-            const PhotonRec p = a.photons[(size_t)r * a.photon_region + i];
-            const LineDev& L = a.lines[p.line];
-            const int n = L.n_cells;
-            const double ud = (double)p.u_pre;
-            const double qd = sqrt(1.0 + 2.0 * (double)p.b);
-            const double eps = sqrt(1.0 + ud * ud) * (2.0 * (double)p.b) / (qd * (1.0 + qd));
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwave = (gridDim.x * blockDim.x) >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // region fills, one per lane (PHOTON_REPL == 64), read once per wavefront
+    static_assert(PHOTON_REPL == 64, "one photon region per lane");
+    const int np_lane = min(a.n_photons[lane], a.photon_region);
+    if (__ballot(np_lane > 0) == 0ull) return;
+    for (int r = 0; r < PHOTON_REPL; ++r) {
+        const int np = __shfl(np_lane, r, 64);
+        for (int i0 = wave * 64; i0 < np; i0 += nwave * 64) {
+            const int i = i0 + lane;
+            const bool valid = i < np;
+            PhotonRec p{};
+            if (valid) p = a.photons[(size_t)r * a.photon_region + i];
             int cs = p.cell;
             float os = p.off;
-            bool ok = true;
-            if (a.conversion != 0) {
-                const double* rc = a.rc_nodes + L.node_base + p.cell;
-                const double rcx = fma((double)p.off, rc[1] - rc[0], rc[0]);
-                const double sp = (double)p.cell + (double)p.off +
-                                  (double)p.dir * rcx * L.inv_ds * asin(fmin(2.0 / eps, 1.0));
-                ok = (sp >= 0.0) && (sp < (double)n);
-                cs = ok ? (int)floor(sp) : 0;
-                os = ok ? (float)(sp - (double)cs) : 0.0f;
-                if (os >= 1.0f) { os = 0.0f; cs += 1; ok = ok && cs < n; }
-            }
-            bool made = false;
-            if (ok) {
-                const int* hc = hist_in + 4 * (size_t)(L.cell_base + cs);
-                if ((float)(hc[0] + hc[1] + hc[2] + hc[3]) < L.nmax) {
+            bool convert = false;
+            float up = 0.0f;
+            if (valid) {
+                const LineDev& L = a.lines[p.line];
+                const int n = L.n_cells;
+                const double ud = (double)p.u_pre;
+                const double qd = sqrt(1.0 + 2.0 * (double)p.b);
+                const double eps = sqrt(1.0 + ud * ud) * (2.0 * (double)p.b) / (qd * (1.0 + qd));
+                bool ok = true;
+                if (a.conversion != 0) {
+                    const double* rc = a.rc_nodes + L.node_base + p.cell;
+                    const double rcx = fma((double)p.off, rc[1] - rc[0], rc[0]);
+                    const double sp = (double)p.cell + (double)p.off +
+                                      (double)p.dir * rcx * L.inv_ds * asin(fmin(2.0 / eps, 1.0));
+                    ok = (sp >= 0.0) && (sp < (double)n);
+                    cs = ok ? (int)floor(sp) : 0;
+                    os = ok ? (float)(sp - (double)cs) : 0.0f;
+                    if (os >= 1.0f) { os = 0.0f; cs += 1; ok = ok && cs < n; }
+                }
+                if (ok) {
+                    const int* hc = hist_in + 4 * (size_t)(L.cell_base + cs);
+                    convert = (float)(hc[0] + hc[1] + hc[2] + hc[3]) < L.nmax;
                     const double gp = 0.5 * eps;
-                    const float up = p.dir * (float)sqrt(fmax((gp - 1.0) * (gp + 1.0), 0.0));
+                    up = p.dir * (float)sqrt(fmax((gp - 1.0) * (gp + 1.0), 0.0));
+                }
+            }
+            // one group per line present in the wavefront
+            bool pending = valid;
+            while (true) {
+                const unsigned long long left = __ballot(pending);
+                if (left == 0ull) break;
+                const int leader = __ffsll((long long)left) - 1;
+                const int gl = __shfl(p.line, leader, 64);
+                const bool mine = pending && p.line == gl;
+                const unsigned long long mconv = __ballot(mine && convert);
+                const int nconv = __popcll(mconv);
+                int base_e = 0, base_p = 0;
+                if (lane == leader && nconv > 0) {
+                    base_e = atomicAdd(&a.alloc[4 * gl + 0], nconv);
+                    base_p = atomicAdd(&a.alloc[4 * gl + 1], nconv);
+                }
+                base_e = __shfl(base_e, leader, 64);
+                base_p = __shfl(base_p, leader, 64);
+                bool made = false;
+                if (mine && convert) {
+                    const int rank = __popcll(mconv & below);
+                    const int se = base_e + rank, spp = base_p + rank;
+                    const bool e_ok = se < a.seg_cap[4 * gl + 0], p_ok = spp < a.seg_cap[4 * gl + 1];
+                    if (!e_ok || !p_ok) set_error(&a.sc->err, -3);
                     const uint4 wc = philox4x32_10(make_uint4((uint32_t)step, (uint32_t)p.pid,
                                                               (uint32_t)(p.pid >> 32), STREAM_CHILD), a.key0, a.key1);
-                    const bool e_ok = append_slot(a, 4 * p.line + 0, cs, os, up, id_from_words(wc.x, wc.y));
-                    const bool p_ok = append_slot(a, 4 * p.line + 1, cs, os, up, id_from_words(wc.z, wc.w));
+                    if (e_ok) {
+                        const int64_t k = a.seg_base[4 * gl + 0] + se;
+                        a.cell[k] = cs; a.off[k] = os; a.u[k] = up; a.id[k] = id_from_words(wc.x, wc.y);
+                    }
+                    if (p_ok) {
+                        const int64_t k = a.seg_base[4 * gl + 1] + spp;
+                        a.cell[k] = cs; a.off[k] = os; a.u[k] = up; a.id[k] = id_from_words(wc.z, wc.w);
+                    }
                     if (e_ok && p_ok) {
+                        const LineDev& L = a.lines[gl];
                         int* ho = hist_out + 4 * (size_t)(L.cell_base + cs);
                         atomicAdd(&ho[0], 1);
                         atomicAdd(&ho[1], 1);
@@ -737,9 +771,15 @@ __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
                         made = true;
                     }
                 }
+                const int n_made = __popcll(__ballot(mine && made));
+                const int n_esc = __popcll(__ballot(mine && !made));
+                if (lane == leader) {
+                    const size_t rep = ((size_t)gl * CNT_REPL + (wave & (CNT_REPL - 1))) * NCOUNT;
+                    if (n_made) atomicAdd(&a.counters[rep + 1], (unsigned long long)n_made);
+                    if (n_esc) atomicAdd(&a.counters[rep + 2], (unsigned long long)n_esc);
+                }
+                pending = pending && !mine;
             }
-            const size_t rep = ((size_t)p.line * CNT_REPL + (i & (CNT_REPL - 1))) * NCOUNT;
-            atomicAdd(&a.counters[rep + (made ? 1 : 2)], 1ull);
         }
     }
 }
