@@ -281,7 +281,7 @@ def main():
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate comparison (for profiling its kernels)")
     ap.add_argument("--surrogate-steps", type=int, default=10)
-    ap.add_argument("--mlp-train-steps", type=int, default=50000)
+    ap.add_argument("--mlp-train-steps", type=int, default=200000)
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -305,6 +305,8 @@ def main():
     cfg["rics"] = args.backend
     sim = Pic1D(cfg, device="cuda:0")
     print(f"# init done: {cfg['lines'][0]}", file=sys.stderr, flush=True)
+    tune = sim.autotune(trial_steps=10)        # launch shape and sort interval (results do not depend on them)
+    print(f"# autotuned: {tune}", file=sys.stderr, flush=True)
     r = timed_run(sim, args.steps, args.warmup)
     bytes_per_launch = hbm_bytes_per_launch(r)
     achieved = bytes_per_launch / r["push_avg_s"]
@@ -335,6 +337,7 @@ def main():
                      "bytes_per_launch": bytes_per_launch, "traffic_unit": "bytes/launch",
                      "traffic_over_algorithmic": traffic / bytes_per_launch if traffic else None},
         "kernels_ms": r["kernels_ms"],
+        "autotune": tune,
         "counters": r["counters"],
         "gauss_residual": m1["gauss_residual"],
     }

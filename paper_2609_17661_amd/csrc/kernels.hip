@@ -501,36 +501,57 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
     Counts cnt;
     int cur_line = -1;
     int seg = 0, seg_t0 = 0, seg_t1 = 0;       // segment of the previous tile and its tile range
-    for (WaveWalk ww(total, a.xcd_walk); ww.t < ww.end; ww.t += ww.stride) {
-        const int t = ww.t;
-        if (t < seg_t0 || t >= seg_t1) {
+    // The next tile's particles are fetched (vector loads into registers) before the
+    // current tile's results are stored and its deposit window flushed, so that the
+    // loads are in flight while the stores and atomics drain.
+    WaveWalk ww(total, a.xcd_walk);
+    int f_seg = 0, f_ib = 0, f_nv = 0;
+    int64_t f_base = 0;
+    int4 fc[PUSH_PPT / 4];
+    float4 fo[PUSH_PPT / 4], fu[PUSH_PPT / 4];
+    // (every call assigns all fetched values, so that none stays live across the loop)
+    auto fetch = [&](int t) {
+        const bool have = t < ww.end;
+        if (have && (t < seg_t0 || t >= seg_t1)) {
             seg = find_segment(a.tile_prefix, a.nseg, t);
             seg_t0 = a.tile_prefix[seg];
             seg_t1 = a.tile_prefix[seg + 1];
         }
-        const int line = seg >> 2, sp = seg & 3;
+        f_seg = seg;
+        f_base = a.seg_base[seg];
+        // this lane's PUSH_PPT consecutive particles (vector loads; slots up to the
+        // capacity, a multiple of 256, always exist)
+        f_ib = (t - seg_t0) * PUSH_TILE + lane * PUSH_PPT;
+        f_nv = have ? max(0, min(PUSH_PPT, a.n_cur[seg] - f_ib)) : 0;
+        const int4* cp = reinterpret_cast<const int4*>(a.cell + f_base + f_ib);
+        const float4* op = reinterpret_cast<const float4*>(a.off + f_base + f_ib);
+        const float4* up = reinterpret_cast<const float4*>(a.u + f_base + f_ib);
+#pragma unroll
+        for (int h = 0; h < PUSH_PPT / 4; ++h) {
+            fc[h] = make_int4(DEAD_CELL, DEAD_CELL, DEAD_CELL, DEAD_CELL);
+            fo[h] = make_float4(0.5f, 0.5f, 0.5f, 0.5f);
+            fu[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (f_nv > 0) { fc[h] = cp[h]; fo[h] = op[h]; fu[h] = up[h]; }
+        }
+    };
+    fetch(ww.t);
+    for (; ww.t < ww.end; ww.t += ww.stride) {
+        const int tseg = f_seg, ib = f_ib, nv = f_nv;
+        const int64_t base = f_base;
+        const int line = tseg >> 2, sp = tseg & 3;
         if (line != cur_line) {
             if (cur_line >= 0) counts_flush(a.counters, cur_line, cnt);
             cur_line = line;
         }
         const LineDev L = a.lines[line];
-        const int ncur = a.n_cur[seg];
-        const int64_t base = a.seg_base[seg];
-        // this lane's PUSH_PPT consecutive particles (vector loads; slots up to the
-        // capacity, a multiple of 256, always exist), staged in the wave's LDS slots
-        // [q][lane] so the particle loop indexes them freely without bank conflicts
-        const int ib = (t - seg_t0) * PUSH_TILE + lane * PUSH_PPT;
-        const int nv = max(0, min(PUSH_PPT, ncur - ib));
+        // the fetched particles, staged in the wave's LDS slots [q][lane] so the
+        // particle loop indexes them freely without bank conflicts
         int lo = INT32_MAX, hi = INT32_MIN, first = -1;
         {
-            const int4* cp = reinterpret_cast<const int4*>(a.cell + base + ib);
-            const float4* op = reinterpret_cast<const float4*>(a.off + base + ib);
-            const float4* up = reinterpret_cast<const float4*>(a.u + base + ib);
 #pragma unroll
             for (int h = 0; h < PUSH_PPT / 4; ++h) {
-                int4 ci = make_int4(DEAD_CELL, DEAD_CELL, DEAD_CELL, DEAD_CELL);
-                float4 oi = make_float4(0.5f, 0.5f, 0.5f, 0.5f), ui = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (nv > 0) { ci = cp[h]; oi = op[h]; ui = up[h]; }
+                const int4 ci = fc[h];
+                const float4 oi = fo[h], ui = fu[h];
                 const int cv[4] = {ci.x, ci.y, ci.z, ci.w};
                 const float ov[4] = {oi.x, oi.y, oi.z, oi.w}, uv[4] = {ui.x, ui.y, ui.z, ui.w};
 #pragma unroll
@@ -652,6 +673,7 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
                 }
             }
         }
+        fetch(ww.t + ww.stride);
         // flush the window
         wave_sync();
         for (int cc2 = lane; cc2 < span; cc2 += 64) {
