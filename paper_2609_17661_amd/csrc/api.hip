@@ -326,7 +326,7 @@ int launch_sort(pic1d_state* st) {
     s.cursor = st->cursor; s.new_count = st->new_count; s.sc = st->sc;
     const int pk = prof_begin(st, 4);
     hipLaunchKernelGGL(k_sort_scan, dim3(st->lay.nseg), dim3(1024), 0, st->stream, s);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(st->aux_blocks), dim3(PUSH_TPB), 0, st->stream, s);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(4 * st->aux_blocks), dim3(PUSH_TPB), 0, st->stream, s);
     hipLaunchKernelGGL(k_sort_finish, dim3((st->lay.nseg + 255) / 256), dim3(256), 0, st->stream, s);
     prof_end(st, pk);
     st->cur = o;

@@ -313,7 +313,8 @@ __device__ __forceinline__ MlpRics mlp_rics(const PushArgs& a, const bf16x8* W, 
 // Drag half step with the surrogate force F0 = F(u0) (Sec. 3): damping branch where
 // |F0| tau_min > |u0|; otherwise the implicit midpoint u1 = u0 + (h/4)(F0 + F(u1)),
 // from the explicit start and refined by fixed-point iteration (contraction
-// (h/4)|F'| << 1 on this branch) where (h/2)|F0| exceeds 2^-12 |u0|.  Lanes with
+// (h/4)|F'| << 1 on this branch) where (h/2)|F0| exceeds 2^-12 |u0|, until the
+// next correction, predicted from the secant slope, is below half an ulp.  Lanes with
 // active == false return u0 but still take part in the network evaluations.
 __device__ __forceinline__ float mlp_drag_half(const PushArgs& a, const bf16x8* W, const float* Wb, const LineDev& L,
                                                float u0, float F0, const Geo& g, float sl, float ptilde, bool active,
@@ -328,9 +329,13 @@ __device__ __forceinline__ float mlp_drag_half(const PushArgs& a, const bf16x8* 
         if (__ballot(refine) == 0ull) break;
         const float F1 = mlp_rics(a, W, Wb, u1, g, sl, cnt.mlp).F;
         const float un = fmaf(0.25f * L.h, F0 + F1, u0);
-        const bool moved = fabsf(un - u1) > 0x1.0p-24f * fabsf(un);
+        // the next correction would be (h/4) F' (un - u1); F' from the secant through
+        // the evaluations at u0 and u1.  Stop once it is below half an ulp of un.
+        const float du = u1 - u0;
+        const float slope = du != 0.0f ? (F1 - F0) / du : 0.0f;
+        const bool more = 0.25f * L.h * fabsf(slope) * fabsf(un - u1) > 0x1.0p-25f * fabsf(un);
         u1 = refine ? un : u1;
-        refine = refine && moved;
+        refine = refine && more;
     }
     return active ? u1 : u0;
 }
@@ -989,6 +994,14 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs s) {
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
             const int c = (i < ncur) ? s.cell[base + i] : DEAD_CELL;
             bool pending = (c != DEAD_CELL);
+            // the particle's other fields are read while its slot is being reserved
+            float pof = 0.0f, puv = 0.0f;
+            uint64_t pid = 0;
+            if (pending) {
+                pof = s.off[base + i];
+                puv = s.u[base + i];
+                pid = s.id[base + i];
+            }
             int pos = 0;
             unsigned long long act = __ballot(pending);
             while (act) {
@@ -1002,11 +1015,11 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs s) {
                     pos = basepos + __popcll(m & ((1ull << lane) - 1ull));
                     pending = false;
                     if (pos < cap) {
-                        const int64_t src = base + i, dst = base + pos;
+                        const int64_t dst = base + pos;
                         s.cell2[dst] = c;
-                        s.off2[dst] = s.off[src];
-                        s.u2[dst] = s.u[src];
-                        s.id2[dst] = s.id[src];
+                        s.off2[dst] = pof;
+                        s.u2[dst] = puv;
+                        s.id2[dst] = pid;
                     } else {
                         set_error(&s.sc->err, -3);
                     }
