@@ -46,13 +46,16 @@ PROFILE_HBM = os.path.join(ROOT, "profiles", "k_push_cfg2_table_hbm.md")
 CAL_BYTES = 256 << 20      # bytes read (and written) by one calibration copy
 
 
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "pic1d_dev.h", "rics_dev.h", "mlp_dev.h")
+
+
 def sources_digest():
-    """sha256 over the library sources: HBM counters are only reported for the
-    kernel they were taken on."""
+    """sha256 over the sources that define the particle kernel: HBM counters are
+    only reported for the kernel they were taken on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2609_17661_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)) + [os.path.join(ROOT, "include", "pic1d.h")]
+    files = [os.path.join(csrc, f) for f in KERNEL_SOURCES]
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -285,9 +288,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build measures the single-GPU hot path "
-              f"(requested --gpus {args.gpus}); lines would shard across GPUs without per-step "
-              f"communication, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures the hot path on one GPU only (requested --gpus {args.gpus}); "
+              f"field lines would shard across GPUs without per-step communication", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()

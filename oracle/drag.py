@@ -9,7 +9,7 @@ step starts from p0 and
     by Newton-Raphson;
   * otherwise relaxes p1 = p_tilde + (p0 - p_tilde) exp(-dt/(2 tau_min)) with
     the attractor p_tilde = mu / (1 - mu^2)^(1/2).
-Readings (documented with the others in the design doc): the limiter is tested with
+Readings of what the paper leaves open: the limiter is tested with
 F evaluated at p0 and with "<=" so that a particle at rest with zero force
 stays where it is; Newton stops at |delta| <= 1e-14 (1 + |p1|) or after 50
 iterations.  Times are in R*/c (dt = h per step, tau_min in the same unit).

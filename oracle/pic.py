@@ -17,8 +17,8 @@ u = gamma beta (float64) and 64-bit ids; the field E on the n cell centres
 (faces k+1/2); the step counter.  Species: 0 e- pair, 1 e+ pair,
 2 atmospheric e-, 3 ion.  RICS acts on the leptons (species 0-2) only.
 
-One step (Sec. 3; the step order inside the stochastic regime and the other
-readings are listed in the design doc):
+One step (Sec. 3; the order inside the stochastic regime -- kick, draw on the
+post-kick momentum, recoil, move -- is a reading, the paper being silent):
   1. gather E at x^n (linear between cell centres, constant beyond the outer ones);
   2. geometry b, mu, x=r/R*, R_curv at x^n (linear between nodes);
   3. continuous regime (lepton, b < b_thr): drag h/2, Lorentz kick, drag h/2;

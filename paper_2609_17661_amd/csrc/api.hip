@@ -292,7 +292,7 @@ int launch_push(pic1d_state* st) {
         case RICS_EXACT: hipLaunchKernelGGL(k_push<RICS_EXACT>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
         case RICS_TABLE: hipLaunchKernelGGL(k_push<RICS_TABLE>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
         case RICS_MLP: hipLaunchKernelGGL(k_push<RICS_MLP>, dim3(st->push_blocks), dim3(PUSH_TPB_MLP), 0, st->stream, a); break;
-        default: return fail(st, PIC1D_EINVAL, "RICS backend not available in this build");
+        default: return fail(st, PIC1D_EINVAL, "unknown RICS backend");
     }
     prof_end(st, pk);
     return PIC1D_OK;
@@ -951,7 +951,7 @@ int pic1d_rics_eval(pic1d_state* st, int32_t line, int64_t n, const float* s_cel
         case RICS_EXACT: hipLaunchKernelGGL(k_rics_eval<RICS_EXACT>, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
         case RICS_TABLE: hipLaunchKernelGGL(k_rics_eval<RICS_TABLE>, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
         case RICS_MLP: hipLaunchKernelGGL(k_rics_eval_mlp, grid, dim3(256), 0, st->stream, a, line, n, s_cells, u, F, ndot, eps); break;
-        default: return fail(st, PIC1D_EINVAL, "RICS backend not available in this build");
+        default: return fail(st, PIC1D_EINVAL, "unknown RICS backend");
     }
     HIP_TRY(st, hipGetLastError());
     HIP_TRY(st, hipStreamSynchronize(st->stream));
