@@ -107,6 +107,34 @@ __device__ __forceinline__ void operand_from_tiles(const f32x4& t0, const f32x4&
     split3(v, s);
 }
 
+// One 128 -> 128 layer on a 16-sample group: acc[T] = bias + sum_K W(T,K) B(K) over
+// the three terms of B.  The loops run K, term, tile, so that consecutive MFMAs
+// write eight different accumulators (independent chains); each tile still sums
+// in the order K0 hi, K0 mid, K0 lo, K1 hi, ...  bias == nullptr starts from zero.
+template <class WPtr>
+__device__ __forceinline__ void hidden_layer(WPtr w, int base, const float* __restrict__ bias, const Split3 (&op)[4],
+                                             f32x4 (&acc)[8]) {
+    const int lane = threadIdx.x & 63, g = lane >> 4;
+    f32x4 c[8];
+#pragma unroll
+    for (int T = 0; T < 8; ++T)
+        c[T] = bias ? *reinterpret_cast<const f32x4*>(bias + 16 * T + 4 * g) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int K = 0; K < 4; ++K) {
+        bf16x8 wt[8];
+#pragma unroll
+        for (int T = 0; T < 8; ++T) wt[T] = w[(base + T * 4 + K) * 64 + lane];
+#pragma unroll
+        for (int T = 0; T < 8; ++T) c[T] = mfma(wt[T], op[K].hi, c[T]);
+#pragma unroll
+        for (int T = 0; T < 8; ++T) c[T] = mfma(wt[T], op[K].mid, c[T]);
+#pragma unroll
+        for (int T = 0; T < 8; ++T) c[T] = mfma(wt[T], op[K].lo, c[T]);
+    }
+#pragma unroll
+    for (int T = 0; T < 8; ++T) acc[T] = c[T];
+}
+
 // Forward pass of one 16-sample group.  `bin` is the input operand of this
 // lane; returns D of the output layer (lanes g == 0: outputs 0..2 of sample r).
 // With STORE, the pre-activations of the four hidden layers are written to
@@ -141,18 +169,7 @@ __device__ __forceinline__ f32x4 mlp_group_forward(WPtr wf, const float* __restr
         }
         const float* bl = bias + MLP_W * (h + 1);
         const int base = FT_H0 + 32 * h;
-#pragma unroll
-        for (int T = 0; T < 8; ++T) {
-            f32x4 c = *reinterpret_cast<const f32x4*>(bl + 16 * T + 4 * g);
-#pragma unroll
-            for (int K = 0; K < 4; ++K) {
-                const bf16x8 w = wf[(base + T * 4 + K) * 64 + lane];
-                c = mfma(w, op[K].hi, c);
-                c = mfma(w, op[K].mid, c);
-                c = mfma(w, op[K].lo, c);
-            }
-            acc[T] = c;
-        }
+        hidden_layer(wf, base, bl, op, acc);
     }
     if (STORE) {
 #pragma unroll
@@ -170,16 +187,20 @@ __device__ __forceinline__ f32x4 mlp_group_forward(WPtr wf, const float* __restr
         }
         operand_from_tiles(a0, a1, op[K]);
     }
-    f32x4 out;
+    // one output tile: three partial sums (one per term) keep three MFMA chains in flight
+    f32x4 o_hi, o_mid = {0.0f, 0.0f, 0.0f, 0.0f}, o_lo = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) out[j] = (g == 0 && j < 3) ? bias[4 * MLP_W + j] : 0.0f;
+    for (int j = 0; j < 4; ++j) o_hi[j] = (g == 0 && j < 3) ? bias[4 * MLP_W + j] : 0.0f;
 #pragma unroll
     for (int K = 0; K < 4; ++K) {
         const bf16x8 w = wf[(FT_OUT + K) * 64 + lane];
-        out = mfma(w, op[K].hi, out);
-        out = mfma(w, op[K].mid, out);
-        out = mfma(w, op[K].lo, out);
+        o_hi = mfma(w, op[K].hi, o_hi);
+        o_mid = mfma(w, op[K].mid, o_mid);
+        o_lo = mfma(w, op[K].lo, o_lo);
     }
+    f32x4 out;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = o_hi[j] + (o_mid[j] + o_lo[j]);
     return out;
 }
 
@@ -233,18 +254,7 @@ __device__ __forceinline__ void mlp_group_backward(WPtr wb, const f32x4& dout, c
 #pragma unroll
         for (int K = 0; K < 4; ++K) operand_from_tiles(acc[2 * K], acc[2 * K + 1], op[K]);
         const int base = BT_H0 + 32 * (h - 1);          // W_{h+1}^T maps dL/dz_h to dL/da_{h-1}
-#pragma unroll
-        for (int T = 0; T < 8; ++T) {
-            f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int K = 0; K < 4; ++K) {
-                const bf16x8 w = wb[(base + T * 4 + K) * 64 + lane];
-                c = mfma(w, op[K].hi, c);
-                c = mfma(w, op[K].mid, c);
-                c = mfma(w, op[K].lo, c);
-            }
-            acc[T] = c;
-        }
+        hidden_layer(wb, base, nullptr, op, acc);
     }
 }
 
