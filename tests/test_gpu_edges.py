@@ -80,3 +80,22 @@ def test_line_without_twist_current():
     sim = Pic1D(cfg)
     total = _steps_match(sim, cfg, n=3)
     assert total["excused"] <= max(3, 1e-2 * total["compared"])
+
+
+def test_nonfinite_momentum_freezes_the_state():
+    from paper_2609_17661_amd import Pic1dError
+    from paper_2609_17661_amd.pic1d import STATUS
+    cfg = workloads.small(r_eq=4.0, n_cells=64, ppc=4, init="hot", rics="exact")
+    sim = Pic1D(cfg)
+    sim.step(1)
+    E = sim.get_field(0)
+    E[10] = 1e300                   # finite in float64, infinite in the float32 copy the gather reads
+    sim.set_field(0, E)
+    with pytest.raises(Pic1dError) as err:
+        sim.step(1)
+    assert STATUS[err.value.code] == "ENONFINITE"
+    with pytest.raises(Pic1dError) as err2:
+        sim.step(1)
+    assert STATUS[err2.value.code] == "ESTATE"
+    m = sim.moments(0)               # still readable
+    assert m["step"] >= 1
