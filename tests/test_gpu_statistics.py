@@ -85,3 +85,32 @@ def test_pair_yield_matches_oracle_within_three_sigma():
     assert o > 100
     assert abs(g - o) <= 3.0 * math.sqrt(o)
     assert abs(e_g - e_o) <= 3.0 * math.sqrt(e_o)
+
+
+def test_cold_two_stream_growth_rate_on_the_gpu():
+    """Linear theory, not the oracle: the symmetric cold two-stream instability of e+ at
+    +v0 and e- at -v0 (carrying the twist current exactly) grows at w_b/(2 gamma0^(3/2))
+    near k v0 = (sqrt 3/2) w_b/gamma0^(3/2)."""
+    beta, ppc, n = 0.2, 64, 1024
+    cfg = dict(rics="off", ppc0=float(ppc), j_twist=2 * beta, seed=3,
+               lines=[dict(r_eq=4.0, n_cells=n, ppc_init=ppc, init="stream", init_beta=beta)])
+    sim = Pic1D(cfg)
+    C, d0 = 0.5, 48.0
+    wb = C / d0
+    g0 = 1 / math.sqrt(1 - beta ** 2)
+    v0 = beta * C
+    gth = wb / (2 * g0 ** 1.5)
+    kth = math.sqrt(3) / 2 * wb / g0 ** 1.5 / v0
+    win = np.hanning(n - 400)
+    A, T = [], []
+    for i in range(0, 1001, 20):
+        if i >= 400:
+            A.append(np.abs(np.fft.rfft(sim.get_field(0)[200:n - 200] * win)))
+            T.append(i)
+        sim.step(20)
+    A, T = np.array(A), np.array(T)
+    k = 2 * np.pi * np.fft.rfftfreq(n - 400)
+    rates = np.polyfit(T, np.log(A + 1e-300), 1)[0]
+    band = (k > 0.5 * kth) & (k < 1.5 * kth)
+    _print("two-stream growth", rates[band].max(), "theory", gth)
+    assert rates[band].max() == pytest.approx(gth, rel=0.10)
