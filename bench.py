@@ -10,7 +10,11 @@ timed on the host as a CPU baseline.
 Plain path (the headline `value`): the R_max = 30 line with 65,536 cells, 200
 e-/e+ per cell each (2.6e7 particles), surface atmosphere with ions at
 m_i/m_e = 100, pairs on with curvature conversion, capacity for 1e8 particles,
-TABLE RICS backend.
+TABLE RICS backend.  Launch shape and sort interval from the library's
+autotuner; the timed steps are replayed from 100-step HIP graphs.  The
+per-kernel breakdown and the push kernel's roofline come from HIP events around
+every launch in a profiled window of eagerly launched steps that follows the
+timed region (events cannot bracket kernels inside a replayed graph).
 
 Batched path (`batched`): 256 dipole lines of uneven length and particle count
 (about 7.7e8 particles) in one state, launch shape picked by the library's
@@ -276,6 +280,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--profile-steps", type=int, default=100,
+                    help="eager steps with per-kernel events after the timed region")
     ap.add_argument("--backend", default="table", choices=["table", "exact", "off"])
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -309,9 +315,12 @@ def main():
     print(f"# init done: {cfg['lines'][0]}", file=sys.stderr, flush=True)
     tune = sim.autotune(trial_steps=10)        # launch shape and sort interval (results do not depend on them)
     print(f"# autotuned: {tune}", file=sys.stderr, flush=True)
-    r = timed_run(sim, args.steps, args.warmup)
-    bytes_per_launch = hbm_bytes_per_launch(r)
-    achieved = bytes_per_launch / r["push_avg_s"]
+    sim.set_graph(100)
+    r = timed_run(sim, args.steps, args.warmup, profile=False)
+    # kernel breakdown and roofline: events around every launch, eager launches
+    rp = timed_run(sim, args.profile_steps, 0, profile=True)
+    bytes_per_launch = hbm_bytes_per_launch(rp)
+    achieved = bytes_per_launch / rp["push_avg_s"]
     traffic = measured_traffic(args.backend, args.workload)     # HBM bytes per k_push launch (rocprofv3)
     m0, m1 = r["m0"], r["m1"]
     res = {
@@ -335,10 +344,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK,
                      "traffic": traffic,
-                     "kernel": "k_push", "avg_ms": r["push_avg_s"] * 1e3,
+                     "kernel": "k_push", "avg_ms": rp["push_avg_s"] * 1e3, "launches": rp["launches"],
                      "bytes_per_launch": bytes_per_launch, "traffic_unit": "bytes/launch",
                      "traffic_over_algorithmic": traffic / bytes_per_launch if traffic else None},
-        "kernels_ms": r["kernels_ms"],
+        "graph_steps": 100,
+        "profiled_ms_per_step": rp["ms_per_step"],
+        "kernels_ms": rp["kernels_ms"],
         "autotune": tune,
         "counters": r["counters"],
         "gauss_residual": m1["gauss_residual"],

@@ -116,8 +116,9 @@ typedef struct {
     double b_thr;             /* stochastic regime where b >= b_thr (0.1)    */
     double mass_ratio;        /* m_i / m_e                                   */
     int32_t rics_backend;     /* PIC1D_RICS_*                                */
-    int32_t table_nlg;        /* TABLE: nodes in log10 gamma over [0, 8]     */
-    int32_t table_ns;         /* TABLE: nodes in s                           */
+    int32_t table_nlg;        /* TABLE: nodes in log10 gamma over [0, 8],    */
+                              /*   2..4096; table_nlg * table_ns <= 2^27     */
+    int32_t table_ns;         /* TABLE: nodes in s, 2..65536                 */
     int32_t pairs;            /* 1: photons with E >= 2 m_e c^2 make pairs   */
     int32_t conversion;       /* PIC1D_CONV_*                                */
     int32_t atmosphere;       /* 1: refill the surface layers (Appendix B.1) */

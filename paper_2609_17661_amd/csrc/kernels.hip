@@ -111,24 +111,42 @@ struct PartGeo {
     TabRows rows;
 };
 
-template <int BACKEND, bool DF>
-__device__ __forceinline__ float rics_F(const PushArgs& a, const LineDev& L, float u, const PartGeo& pg, float& dF) {
-    if constexpr (BACKEND == RICS_TABLE) return table_F<DF>(L, a.table + L.table_off, a.nlg, pg.rows, u, dF);
-    else return exact_F<DF>(L, u, pg.g, dF);
+// The line's table and its second row (row j0 + 1 at the same byte offset).
+__device__ __forceinline__ const char* tab_base(const PushArgs& a, const LineDev& L) {
+    return reinterpret_cast<const char*>(a.table + L.table_off);
 }
+
+// F_hat at u with what dF/du needs (evaluated only where the midpoint asks for it).
+template <int BACKEND>
+__device__ __forceinline__ auto rics_eval(const PushArgs& a, const LineDev& L, float u, const PartGeo& pg) {
+    if constexpr (BACKEND == RICS_TABLE) {
+        const char* tb = tab_base(a, L);
+        return table_eval(L, tb, tb + 16 * a.nlg, a.nlg, pg.rows, u);
+    } else {
+        return exact_eval(L, u, pg.g);
+    }
+}
+__device__ __forceinline__ float eval_dF(const LineDev& L, const TableEval& e) { return e.dF(L); }
+__device__ __forceinline__ float eval_dF(const LineDev&, const ExactEval& e) { return e.dF(); }
 
 template <int BACKEND>
 __device__ __forceinline__ float rics_N(const PushArgs& a, const LineDev& L, float u, const PartGeo& pg) {
-    if constexpr (BACKEND == RICS_TABLE) return table_N(L, a.table + L.table_off, a.nlg, pg.rows, u);
-    else return exact_N(L, u, pg.g);
+    if constexpr (BACKEND == RICS_TABLE) {
+        const char* tb = tab_base(a, L);
+        return table_N(L, tb, tb + 16 * a.nlg, a.nlg, pg.rows, u);
+    } else {
+        return exact_N(L, u, pg.g);
+    }
 }
 
+// Geometry and table rows of a particle at x = c0 + o0 in float64 (the general
+// form; the pusher forms the rows per cell where it can).
 template <int BACKEND>
-__device__ __forceinline__ PartGeo part_geo(const LineDev& L, const float4& n0, const float4& n1, float o0, double x,
-                                            int ns) {
+__device__ __forceinline__ PartGeo part_geo(const PushArgs& a, const LineDev& L, const float4& n0, const float4& n1,
+                                            int c0, float o0) {
     PartGeo pg;
     pg.g = geo_lerp(L, n0, n1, o0);
-    if constexpr (BACKEND == RICS_TABLE) pg.rows = table_rows(L, ns, x);
+    if constexpr (BACKEND == RICS_TABLE) pg.rows = table_rows(L, a.ns, 16 * a.nlg, (double)c0 + (double)o0);
     return pg;
 }
 
@@ -140,22 +158,13 @@ __device__ __forceinline__ float newton_midpoint(const PushArgs& a, const LineDe
     const float hq = 0.25f * L.h;
 #pragma unroll 1
     for (int it = 0; it < 4; ++it) {
-        float dF1;
-        const float F1 = rics_F<BACKEND, true>(a, L, u1, g, dF1);
-        const float G = u1 - u0 - hq * (F0 + F1);
-        const float del = G / (1.0f - hq * dF1);
+        const auto e1 = rics_eval<BACKEND>(a, L, u1, g);
+        const float G = u1 - u0 - hq * (F0 + e1.F);
+        const float del = G / (1.0f - hq * eval_dF(L, e1));
         u1 -= del;
         if (fabsf(del) <= 0x1.0p-24f * fabsf(u1)) break;
     }
     return u1;
-}
-
-template <int BACKEND>
-__device__ __forceinline__ bool needs_newton(const PushArgs& a, const LineDev& L, float u0, float F0, float u1,
-                                          const PartGeo& g) {
-    float dF0;
-    (void)rics_F<BACKEND, true>(a, L, u0, g, dF0);
-    return 0.25f * L.h * fabsf(dF0) * 0.5f * L.h * fabsf(F0) > 0x1.0p-25f * fabsf(u1);
 }
 
 // One drag update over h/2 (Sec. 3): implicit midpoint where |F(p0)| tau_min <= |p0|,
@@ -165,21 +174,19 @@ __device__ __forceinline__ bool needs_newton(const PushArgs& a, const LineDev& L
 template <int BACKEND>
 __device__ __forceinline__ float drag_half(const PushArgs& a, const LineDev& L, float u0, const PartGeo& g,
                                            float ptilde, bool alive, int& n_limited, int& n_newton) {
-    float unused;
-    const float F0 = rics_F<BACKEND, false>(a, L, u0, g, unused);
-    if (fabsf(F0) * L.tau_hat <= fabsf(u0)) {
-        float u1 = fmaf(0.5f * L.h, F0, u0);
-        // |(h/2) F0| <= |u0| h / (2 tau_min): below float32 resolution of the Newton
-        // correction whenever (h/2) |F0| itself is tiny; otherwise ask the derivative
-        if (F0 != 0.0f && 0.5f * L.h * fabsf(F0) > 0x1.0p-12f * fabsf(u0) &&
-            needs_newton<BACKEND>(a, L, u0, F0, u1, g)) {
-            n_newton += alive ? 1 : 0;
-            u1 = newton_midpoint<BACKEND>(a, L, u0, F0, u1, g);
-        }
-        return u1;
+    const auto e0 = rics_eval<BACKEND>(a, L, u0, g);
+    const float F0 = e0.F;
+    const bool implicit = fabsf(F0) * L.tau_hat <= fabsf(u0);
+    float u1 = implicit ? fmaf(0.5f * L.h, F0, u0) : fmaf(-(u0 - ptilde), L.damp, u0);
+    n_limited += (alive && !implicit) ? 1 : 0;
+    // |(h/2) F0| <= |u0| h / (2 tau_min): below float32 resolution of the Newton
+    // correction whenever (h/2) |F0| itself is tiny; otherwise ask the derivative
+    if (implicit && F0 != 0.0f && 0.5f * L.h * fabsf(F0) > 0x1.0p-12f * fabsf(u0) &&
+        0.25f * L.h * fabsf(eval_dF(L, e0)) * 0.5f * L.h * fabsf(F0) > 0x1.0p-25f * fabsf(u1)) {
+        n_newton += alive ? 1 : 0;
+        u1 = newton_midpoint<BACKEND>(a, L, u0, F0, u1, g);
     }
-    n_limited += alive ? 1 : 0;
-    return fmaf(-(u0 - ptilde), L.damp, u0);
+    return u1;
 }
 
 // Per-tile constants of the pusher (species of the tile, step, count buffers).
@@ -342,50 +349,74 @@ __device__ __forceinline__ float mlp_drag_half(const PushArgs& a, const bf16x8* 
 
 // Field and geometry of the cell a lane is working in.  A lane's particles are
 // consecutive in cell order, so the cache is reloaded only when the cell changes.
-// The neighbours of E are clamped at the walls, which makes the gather constant
-// beyond the outermost cell centres.
+// The kick q E / (m C) is kept as its value at the cell centre and its change per
+// cell towards the neighbouring centres, whose E is clamped at the walls (the
+// gather is constant beyond the outermost cell centres).  The table backend
+// keeps the per-cell part of the particle's table rows: for offset o the row
+// position is rows0.pos.wj + o s_scale (u >= 0) and rows0.neg.wj - o s_scale
+// (mirrored), valid for the whole cell where rows_simple (the cell lies between
+// two rows, clear of the clamped ends).
 struct CellCache {
     int cell;
-    float Em, E0, Ep;       // E at the centres of cells c-1, c, c+1
+    float K0, KsL, KsU;
     float4 n0, n1;          // geometry nodes c, c+1
+    TabRows rows0;
+    bool rows_simple;
 };
 
-template <bool GEO>
-__device__ __forceinline__ void cache_load(CellCache& cc, const PushArgs& a, const LineDev& L, int c0) {
+template <int BACKEND>
+__device__ __forceinline__ void cache_load(CellCache& cc, const PushArgs& a, const LineDev& L, float qmC, int c0) {
     cc.cell = c0;
     const float* E = a.E32 + L.cell_base;
-    cc.Em = E[max(c0 - 1, 0)];
-    cc.E0 = E[c0];
-    cc.Ep = E[min(c0 + 1, L.n_cells - 1)];
-    if (GEO) {
+    const float Em = E[max(c0 - 1, 0)];
+    const float E0 = E[c0];
+    const float Ep = E[min(c0 + 1, L.n_cells - 1)];
+    cc.K0 = qmC * E0;
+    cc.KsL = qmC * (E0 - Em);
+    cc.KsU = qmC * (Ep - E0);
+    if constexpr (BACKEND != RICS_OFF) {
         cc.n0 = a.nodes[L.node_base + c0];
         cc.n1 = a.nodes[L.node_base + c0 + 1];
+    }
+    if constexpr (BACKEND == RICS_TABLE) {
+        const double sc = L.s_scale;
+        const double fp = fma((double)c0, sc, -0.5);
+        const double fn = fma((double)(L.n_cells - c0), sc, -0.5);
+        const double jp = floor(fp), jn = floor(fn);
+        const double top = (double)(a.ns - 2);
+        constexpr double M = 0x1.0p-20;      // margin for the float32 row weight
+        cc.rows_simple = jp >= 0.0 && jp <= top && fp + sc <= jp + 1.0 - M &&
+                         jn >= 0.0 && jn <= top && fn - sc >= jn + M;
+        const int nlg16 = 16 * a.nlg;
+        cc.rows0.pos.off = cc.rows_simple ? (int)jp * nlg16 : 0;
+        cc.rows0.pos.wj = (float)(fp - jp);
+        cc.rows0.neg.off = cc.rows_simple ? (int)jn * nlg16 : 0;
+        cc.rows0.neg.wj = (float)(fn - jn);
     }
 }
 
 // Everything one particle does in one step: gather, RICS, kick, move, and the
 // deposit of its path in fixed point.  Written without data-dependent branches on
-// the common path (dead lanes compute on sanitised inputs and deposit nothing).
-// Returns the new cell (DEAD_CELL when absorbed) in c1, d = c1 - c0 in {-1, 0, 1},
-// and the path's overlaps with cells c0-1, c0, c0+1 in units of 2^-28 cell
-// (unsigned by the charge; jm and jp vanish unless the path leaves the cell).
+// the common path.  Dead slots (absorbed particles and the padding of a partial
+// tile) enter at o0 = 1/2, u = 0, are held at u = 0, and so stay in their cell and
+// deposit nothing.  c0 is the cached cell.
+// Returns the new cell (DEAD_CELL when absorbed or dead) in c1, d = c1 - c0 in
+// {-1, 0, 1}, and the path's overlaps with cells c0-1, c0, c0+1 in units of 2^-28
+// cell (unsigned by the charge; jm and jp vanish unless the path leaves the cell).
 template <int BACKEND>
 __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDev& L, const TileCtx& T,
                                                  const CellCache& cc, bool alive, int line, int sp, int64_t k,
                                                  int c0, float o0, float& u, Counts& cnt, int& c1, float& o1,
-                                                 int& jm, int& j0, int& jp, int& d, const bf16x8* W,
+                                                 int& jm, int& j0, int& jp, int& d, bool& gone, const bf16x8* W,
                                                  const float* Wb) {
     const int n = L.n_cells;
     constexpr bool RICS = BACKEND != RICS_OFF;
 
-    // field gather: E at x^n, linear between cell centres
-    const bool upper = o0 >= 0.5f;
-    const float Ea = upper ? cc.E0 : cc.Em;
-    const float Eb = upper ? cc.Ep : cc.E0;
-    const float w = upper ? o0 - 0.5f : o0 + 0.5f;
-    float kick = T.qm * fmaf(w, Eb - Ea, Ea) * L.invC;
-    const double x = (double)c0 + (double)o0;
+    // field gather: E at x^n, linear between cell centres (as the kick per step)
+    const float ws = o0 - 0.5f;
+    float kick = fmaf(ws, ws >= 0.0f ? cc.KsU : cc.KsL, cc.K0);
     if (T.gravity) {
+        const double x = (double)c0 + (double)o0;
         const double dw = fmin(x, (double)n - x);
         const float gk = ((x < (double)L.half_n) ? -1.0f : 1.0f) * L.grav * T.inv_mass;
         kick += (dw <= L.atm_depth) ? gk : 0.0f;
@@ -394,7 +425,7 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
     if constexpr (BACKEND == RICS_MLP) {
         if (sp != 3) {            // wave-uniform: a tile holds one species
             const Geo g = geo_lerp(L, cc.n0, cc.n1, o0);
-            const float sl = (float)(x / (double)n);
+            const float sl = (float)(((double)c0 + (double)o0) / (double)n);
             const bool cont = g.b < L.b_thr;
             const float pt = g.mu * frsq(fmaxf(fmaf(-g.mu, g.mu, 1.0f), 1e-30f));
             const MlpRics ra = mlp_rics(a, W, Wb, u, g, sl, cnt.mlp);
@@ -407,7 +438,18 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
             u += kick;
         }
     } else if (RICS && sp != 3) {
-        const PartGeo pg = part_geo<BACKEND>(L, cc.n0, cc.n1, o0, x, a.ns);
+        PartGeo pg;
+        pg.g = geo_lerp(L, cc.n0, cc.n1, o0);
+        if constexpr (BACKEND == RICS_TABLE) {
+            if (cc.rows_simple) {
+                pg.rows.pos.off = cc.rows0.pos.off;
+                pg.rows.pos.wj = fmaf(o0, L.s_scale_f, cc.rows0.pos.wj);
+                pg.rows.neg.off = cc.rows0.neg.off;
+                pg.rows.neg.wj = fmaf(-o0, L.s_scale_f, cc.rows0.neg.wj);
+            } else {
+                pg.rows = table_rows(L, a.ns, 16 * a.nlg, (double)c0 + (double)o0);
+            }
+        }
         if (pg.g.b < L.b_thr) {
             // continuous regime: Strang splitting drag h/2, Lorentz kick, drag h/2, both
             // at x^n; the damping branch relaxes towards p_tilde = mu / (1 - mu^2)^(1/2)
@@ -422,15 +464,18 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
     } else {
         u += kick;
     }
-    if (alive && !isfinite(u)) set_error(&a.sc->err, -5);
+    u = alive ? u : 0.0f;
+    if (!isfinite(u)) set_error(&a.sc->err, -5);
 
     // move x^{n+1} = x^n + C u / gamma with the offset carried into the cell index
-    o1 = fmaf(L.C * u, frsq(fmaf(u, u, 1.0f)), o0);
-    const int up = o1 >= 1.0f, dn = o1 < 0.0f;
-    o1 = o1 - (float)up + (float)dn;          // exact for o1 in [1, 1.5); o1 + 1 may round up to 1
-    const int fix = o1 >= 1.0f;
+    // (|C u / gamma| < 1/2, so the carry is -1, 0 or 1 and o1 - carry is exact; o1 + 1
+    // may round up to 1)
+    const float o1r = fmaf(L.C * u, frsq(fmaf(u, u, 1.0f)), o0);
+    const float carry = floorf(o1r);
+    o1 = o1r - carry;
+    const bool fix = o1 >= 1.0f;
     o1 = fix ? 0.0f : o1;
-    d = up - dn + fix;
+    d = (int)carry + (fix ? 1 : 0);
     c1 = c0 + d;
     // fixed-point deposit of the path from the stored old and new offsets quantised
     // to 2^-28 cell: X1 is the new position relative to the old cell's left face.
@@ -439,13 +484,13 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
     // in cells -1 or n, which the flush drops.
     constexpr int ONE = 1 << POS_BITS;
     const int f0 = (int)(o0 * POS_SCALE);
-    int X1 = d * ONE + (int)(o1 * POS_SCALE);
-    X1 = alive ? X1 : f0;
+    const int X1 = d * ONE + (int)(o1 * POS_SCALE);
     jm = min(X1, 0);
     j0 = min(max(X1, 0), ONE) - f0;
     jp = max(X1 - ONE, 0);
-    const bool gone = c1 < 0 || c1 >= n;
-    cnt.absorbed += (alive && gone) ? 1 : 0;
+    const bool out = (unsigned)c1 >= (unsigned)n;
+    cnt.absorbed += (alive && out) ? 1 : 0;
+    gone = out || !alive;
     c1 = gone ? DEAD_CELL : c1;
 }
 
@@ -496,7 +541,6 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
         __syncthreads();
     }
     if (a.sc->err != 0) return;
-    constexpr bool GEO = BACKEND != RICS_OFF;
     const uint64_t step = a.sc->step;
     const int32_t* hist_in = (step & 1) ? a.hist[1] : a.hist[0];
     int32_t* hist_out = (step & 1) ? a.hist[0] : a.hist[1];
@@ -511,6 +555,7 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
     // loads are in flight while the stores and atomics drain.
     WaveWalk ww(total, a.xcd_walk);
     int f_seg = 0, f_ib = 0, f_nv = 0;
+    bool f_full = false;
     int64_t f_base = 0;
     int4 fc[PUSH_PPT / 4];
     float4 fo[PUSH_PPT / 4], fu[PUSH_PPT / 4];
@@ -526,8 +571,11 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
         f_base = a.seg_base[seg];
         // this lane's PUSH_PPT consecutive particles (vector loads; slots up to the
         // capacity, a multiple of 256, always exist)
-        f_ib = (t - seg_t0) * PUSH_TILE + lane * PUSH_PPT;
-        f_nv = have ? max(0, min(PUSH_PPT, a.n_cur[seg] - f_ib)) : 0;
+        const int t0 = (t - seg_t0) * PUSH_TILE;
+        const int ncur = a.n_cur[seg];
+        f_full = have && ncur - t0 >= PUSH_TILE;        // wave-uniform
+        f_ib = t0 + lane * PUSH_PPT;
+        f_nv = have ? max(0, min(PUSH_PPT, ncur - f_ib)) : 0;
         const int4* cp = reinterpret_cast<const int4*>(a.cell + f_base + f_ib);
         const float4* op = reinterpret_cast<const float4*>(a.off + f_base + f_ib);
         const float4* up = reinterpret_cast<const float4*>(a.u + f_base + f_ib);
@@ -550,9 +598,14 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
         }
         const LineDev L = a.lines[line];
         // the fetched particles, staged in the wave's LDS slots [q][lane] so the
-        // particle loop indexes them freely without bank conflicts
-        int lo = INT32_MAX, hi = INT32_MIN, first = -1;
-        {
+        // particle loop indexes them freely without bank conflicts.  Dead slots are
+        // stored as (DEAD_CELL, 1/2, 0); the padding of a partial tile is made so.
+        // The lane's cell range: DEAD_CELL is the largest cell as unsigned and the
+        // smallest as signed, so neither bound sees it.
+        unsigned lo_u = 0xffffffffu;
+        int hi_s = INT32_MIN;
+        int cst[PUSH_PPT];
+        auto stage = [&](auto full) {
 #pragma unroll
             for (int h = 0; h < PUSH_PPT / 4; ++h) {
                 const int4 ci = fc[h];
@@ -562,21 +615,46 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int q = 4 * h + i;
-                    const int c = q < nv ? cv[i] : DEAD_CELL;
-                    if (c != DEAD_CELL) {
-                        lo = min(lo, c - 1);
-                        hi = max(hi, c + 1);
-                        if (first < 0) first = c;
-                    }
+                    const bool valid = decltype(full)::value || q < nv;
+                    const int c = valid ? cv[i] : DEAD_CELL;
+                    cst[q] = c;
+                    lo_u = min(lo_u, (unsigned)c);
+                    hi_s = max(hi_s, c);
                     sPc[wid][q][lane] = c;
-                    sPo[wid][q][lane] = ov[i];
-                    sPu[wid][q][lane] = uv[i];
+                    sPo[wid][q][lane] = valid ? ov[i] : 0.5f;
+                    sPu[wid][q][lane] = valid ? uv[i] : 0.0f;
                 }
             }
+        };
+        if (f_full) stage(std::true_type{});
+        else stage(std::false_type{});
+        const bool lane_any = hi_s >= 0;
+        const int first = lane_any ? (int)lo_u : 0;
+        // The order in which the lane visits its slots: by cell (dead slots last), so
+        // that the run accumulator and the cell cache see each cell once however the
+        // particles of a cell are ordered in memory.  A 19-comparator sorting network
+        // on keys (cell - first) * 8 + slot; the slot order is packed in 3-bit fields.
+        static_assert(PUSH_PPT == 8, "the visit order packs 8 slots in 3-bit fields");
+        uint32_t visit = 0;
+        {
+            uint32_t k[PUSH_PPT];
+#pragma unroll
+            for (int q = 0; q < PUSH_PPT; ++q)
+                k[q] = (cst[q] == DEAD_CELL ? 0xfffffff8u : (uint32_t)(cst[q] - first) << 3) | (uint32_t)q;
+            constexpr int NET[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
+                                        {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+            for (int e = 0; e < 19; ++e) {
+                const uint32_t x = k[NET[e][0]], y = k[NET[e][1]];
+                k[NET[e][0]] = min(x, y);
+                k[NET[e][1]] = max(x, y);
+            }
+#pragma unroll
+            for (int q = 0; q < PUSH_PPT; ++q) visit |= (k[q] & 7u) << (3 * q);
         }
         // window [lo, hi] of cells this wavefront's deposit can touch
-        lo = wave_min_i(lo);
-        hi = wave_max_i(hi);
+        int lo = wave_min_i(lane_any ? (int)lo_u - 1 : INT32_MAX);
+        int hi = wave_max_i(lane_any ? hi_s + 1 : INT32_MIN);
         const bool any = lo <= hi;
         lo = any ? max(lo, 0) : 0;
         hi = any ? min(hi, L.n_cells - 1) : -1;
@@ -597,11 +675,12 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
         T.inv_mass = (sp == 3) ? a.inv_mass_ion : 1.0f;
         T.gravity = a.gravity && any && ((double)lo <= L.atm_depth + 1.0 ||
                                          (double)(L.n_cells - 1 - hi) <= L.atm_depth + 1.0);
+        const float qmC = T.qm * L.invC;
         unsigned long long* Jg = a.J + L.cell_base;
         int* Hg = hist_out + 4 * (size_t)L.cell_base + sp;
 
         CellCache cc;
-        cache_load<GEO>(cc, a, L, first >= 0 ? first : 0);
+        cache_load<BACKEND>(cc, a, L, qmC, first);
         // per-lane run accumulator over consecutive particles of one cell: deposits
         // (2^-28 cell) into cells key-1, key, key+1 and the new-cell counts of the same
         // three cells packed in 10-bit fields of hc
@@ -628,29 +707,29 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
         };
 #pragma unroll 1
         for (int q = 0; q < PUSH_PPT; ++q) {
-            const int c0 = sPc[wid][q][lane];
+            const int slot = (visit >> (3 * q)) & 7;
+            const int c0 = sPc[wid][slot][lane];
             const bool alive = c0 != DEAD_CELL;
             if (alive && c0 != cc.cell) {
                 flush_run();
-                cache_load<GEO>(cc, a, L, c0);
+                cache_load<BACKEND>(cc, a, L, qmC, c0);
                 key = c0;
             }
-            const float u0 = sPu[wid][q][lane];
-            const float o0 = sPo[wid][q][lane];
-            float uq = alive ? u0 : 0.0f;
-            const float oq = alive ? o0 : 0.5f;
+            float uq = sPu[wid][slot][lane];
+            const float oq = sPo[wid][slot][lane];
             int c1, d, jm, j0, jp;
             float o1;
-            advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + q, cc.cell, oq, uq, cnt, c1, o1,
-                                      jm, j0, jp, d, sW, sWb);
+            bool gone;
+            advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1,
+                                      o1, jm, j0, jp, d, gone, sW, sWb);
             cnt.pushed += alive ? 1 : 0;
             jv0 += jm;
             jv1 += j0;
             jv2 += jp;
             hc += alive ? (1 << (10 * (d + 1))) : 0;
-            sPc[wid][q][lane] = alive ? c1 : DEAD_CELL;
-            sPo[wid][q][lane] = (alive && c1 != DEAD_CELL) ? o1 : o0;
-            sPu[wid][q][lane] = alive ? uq : u0;
+            sPc[wid][slot][lane] = c1;
+            sPo[wid][slot][lane] = gone ? 0.5f : o1;
+            sPu[wid][slot][lane] = gone ? 0.0f : uq;
         }
         flush_run();
         // write back (vector stores for full groups; never touch slots >= ncur, where
@@ -1159,13 +1238,12 @@ __global__ __launch_bounds__(256) void k_rics_eval(PushArgs a, int line, int64_t
     const float s = fminf(fmaxf(s_cells[i], 0.0f), (float)L.n_cells);
     const int c0 = min((int)floorf(s), L.n_cells - 1);
     const float o0 = s - (float)c0;
-    const double x = (double)c0 + (double)o0;
-    const PartGeo pg = part_geo<BACKEND>(L, a.nodes[L.node_base + c0], a.nodes[L.node_base + c0 + 1], o0, x, a.ns);
+    const PartGeo pg = part_geo<BACKEND>(a, L, a.nodes[L.node_base + c0], a.nodes[L.node_base + c0 + 1], c0, o0);
     const Geo& g = pg.g;
     const float u = uin[i];
-    float f = 0.0f, nd = 0.0f, unused;
+    float f = 0.0f, nd = 0.0f;
     if constexpr (BACKEND != RICS_OFF) {
-        f = rics_F<BACKEND, false>(a, L, u, pg, unused);
+        f = rics_eval<BACKEND>(a, L, u, pg).F;
         nd = rics_N<BACKEND>(a, L, u, pg);
     }
     F[i] = f;

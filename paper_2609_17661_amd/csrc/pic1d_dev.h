@@ -53,9 +53,9 @@ struct LineDev {
     float grav;           // T C / h_atm: |du| per step of a unit-mass particle in the layer
     float nmax;           // n_max per cell (all species)
     float half_n;         // n_cells / 2
-    float lgk;            // table: (nlg - 1)/8 log10(2): fractional column per unit log2 gamma
+    float lgk;            // table: (nlg - 1)/16 log10(2): fractional column per unit log2 gamma^2
     float lgk_hi, lgk_lo; // lgk split into a 10-fraction-bit head and the rest
-    float pad1;
+    float s_scale_f;      // table: s_scale in float32 (rows per cell)
     double s_scale;       // table: ns / n_cells
     double lg_scale;      // table: (nlg - 1) / 8
     double atm_depth;     // gravity layer depth (cells from each wall)

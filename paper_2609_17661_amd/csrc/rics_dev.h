@@ -32,28 +32,36 @@ struct Geo {
     float ix2;    // (R* / r)^2
 };
 
-// F_hat and, if DF, dF/du of the closed form.  With w = gamma mu - u and
+// F_hat of the closed form at u, with what dF/du needs.  With w = gamma mu - u and
 // d = gamma - u mu: dw/du = -(d/gamma), dy/du = y w / (gamma d),
 // d(y^3/(e^y-1))/dy = g3 (3/y - 1 - 1/(e^y - 1)).
-template <bool DF>
-__device__ __forceinline__ float exact_F(const LineDev& L, float u, const Geo& g, float& dF) {
-    const float gam = fsqrt(fmaf(u, u, 1.0f));
-    const float d = fmaf(-u, g.mu, gam);
-    const float y = g.by * frcp(d);
-    if (!(y <= Y_CUT)) {
-        if (DF) dF = 0.0f;
-        return 0.0f;
-    }
-    const float r = frcp(expm1f(y));
-    const float g3 = y * y * y * r;
-    const float w = fmaf(gam, g.mu, -u);
-    const float A = L.A_F * g.ix2;
-    if (DF) {
+struct ExactEval {
+    float F;
+    float gam, d, y, r, w, Ag3;     // (Ag3 = A_F x^-2 y^3 / (e^y - 1))
+    bool inside;                    // below the Planck cutoff (else F = dF/du = 0)
+    __device__ __forceinline__ float dF() const {
+        if (!inside) return 0.0f;
         const float ig = frcp(gam);
         const float dy = y * w * ig * frcp(d);
-        dF = A * g3 * (-(d * ig) + w * (3.0f * frcp(y) - 1.0f - r) * dy);
+        return Ag3 * (-(d * ig) + w * (3.0f * frcp(y) - 1.0f - r) * dy);
     }
-    return A * w * g3;
+};
+
+__device__ __forceinline__ ExactEval exact_eval(const LineDev& L, float u, const Geo& g) {
+    ExactEval e;
+    e.gam = fsqrt(fmaf(u, u, 1.0f));
+    e.d = fmaf(-u, g.mu, e.gam);
+    e.y = g.by * frcp(e.d);
+    e.inside = e.y <= Y_CUT;
+    e.r = e.w = e.Ag3 = 0.0f;
+    e.F = 0.0f;
+    if (e.inside) {
+        e.r = frcp(expm1f(e.y));
+        e.Ag3 = L.A_F * g.ix2 * (e.y * e.y * e.y * e.r);
+        e.w = fmaf(e.gam, g.mu, -u);
+        e.F = e.Ag3 * e.w;
+    }
+    return e;
 }
 
 __device__ __forceinline__ float exact_N(const LineDev& L, float u, const Geo& g) {
@@ -63,106 +71,114 @@ __device__ __forceinline__ float exact_N(const LineDev& L, float u, const Geo& g
     return L.A_N * g.ix2 * y * y * frcp(expm1f(y) * gam);
 }
 
-// Table position along s of a particle at x (cells): row j0 and weight wj, for the
-// u >= 0 half (x) and for the mirrored u < 0 half (L - x).  Formed once per
-// particle in float64 (the position does not change during the push).
+// Table rows of a particle: byte offset of row j0 within the line's table and the
+// weight wj of row j0 + 1, for the u >= 0 half at x (cells) and for the mirrored
+// u < 0 half at L - x.  Row j sits at x = (j + 1/2) / s_scale.
 struct TabRow {
-    int j0;
+    int off;        // j0 * nlg * 16
     float wj;
 };
 
-__device__ __forceinline__ TabRow table_row(const LineDev& L, int ns, double xm) {
+struct TabRows {
+    TabRow pos, neg;
+};
+
+// General form, in float64 from the position x (the pusher takes it only where
+// a cell straddles a row or the clamped ends; elsewhere the rows are per cell).
+__device__ __forceinline__ TabRow table_row(const LineDev& L, int ns, int nlg16, double xm) {
     double fj = fma(xm, L.s_scale, -0.5);
     fj = fmin(fmax(fj, 0.0), (double)(ns - 1));
+    const int j0 = min((int)fj, ns - 2);
     TabRow r;
-    r.j0 = min((int)fj, ns - 2);
-    r.wj = (float)(fj - (double)r.j0);
+    r.off = j0 * nlg16;
+    r.wj = (float)(fj - (double)j0);
     return r;
 }
 
-// Column position along log10 gamma: i0 and weight wi.  log2 gamma is split into
-// the exponent ex and log2 of the mantissa; ex * K is formed exactly from a
-// 10-fraction-bit head of K = (nlg-1)/8 * log10(2), so that the weight carries an
-// absolute error of about 1e-6 in float32.
+__device__ __forceinline__ TabRows table_rows(const LineDev& L, int ns, int nlg16, double x) {
+    TabRows r;
+    r.pos = table_row(L, ns, nlg16, x);
+    r.neg = table_row(L, ns, nlg16, (double)L.n_cells - x);
+    return r;
+}
+
+// Column position along log10 gamma: i0 and weight wi.  From gamma^2 = man 2^ex
+// (man in [0.5, 1)): the fractional column is K log2 gamma = (K/2)(ex + log2 man)
+// with K = (nlg-1)/8 log10(2); ex (K/2) is formed exactly from a 10-fraction-bit
+// head of K/2, so that the weight carries an absolute error of about 1e-6 in
+// float32.
 struct TabCol {
     int i0;
     float wi;
+    float g2;         // gamma^2
     bool inside;      // strictly inside the table (derivative non-zero)
 };
 
 __device__ __forceinline__ TabCol table_col(const LineDev& L, int nlg, float ua) {
-    const float gam = fsqrt(fmaf(ua, ua, 1.0f));
-    const unsigned bits = __float_as_uint(gam);
-    const int ex = (int)((bits >> 23) & 0xffu) - 126;                          // gam = man 2^ex
-    const float man = __uint_as_float((bits & 0x007fffffu) | 0x3f000000u);      // man in [0.5, 1)
-    const float l2m = __builtin_amdgcn_logf(man);                                // in [-1, 0)
-    const float head = (float)ex * L.lgk_hi;                                     // exact
-    const float ih = floorf(head);
-    const float r = (head - ih) + fmaf((float)ex, L.lgk_lo, l2m * L.lgk);
-    const float fr = floorf(r);
-    int i0 = (int)ih + (int)fr;
-    float wi = r - fr;
     TabCol c;
-    c.inside = (i0 >= 0) && (i0 < nlg - 1) && !(i0 == 0 && wi == 0.0f);
-    if (i0 < 0) { i0 = 0; wi = 0.0f; }
-    if (i0 > nlg - 2) { i0 = nlg - 2; wi = 1.0f; }
+    c.g2 = fmaf(ua, ua, 1.0f);
+    const int ex = __builtin_amdgcn_frexp_expf(c.g2);
+    const float l2m = __builtin_amdgcn_logf(__builtin_amdgcn_frexp_mantf(c.g2));   // in [-1, 0)
+    const float exf = (float)ex;
+    const float head = exf * L.lgk_hi;                                             // exact
+    const float ih = floorf(head);
+    const float r = (head - ih) + fmaf(exf, L.lgk_lo, l2m * L.lgk);
+    const float fr = floorf(r);
+    const int i = (int)(ih + fr);
+    const int i0 = min(max(i, 0), nlg - 2);
+    // below the table the weight clamps to 0, above it to 1
+    const float wi = fminf(fmaxf((r - fr) + (float)(i - i0), 0.0f), 1.0f);
+    c.inside = (i == i0) && !(i == 0 && wi == 0.0f);
     c.i0 = i0;
     c.wi = wi;
     return c;
 }
 
 // The table is stored as [ns][nlg] float4 {F(i), F(i+1), Ndot(i), Ndot(i+1)} so that
-// one 16-byte gather per row brings both columns of both quantities.
-struct TabVal {
-    float F, slopeF, N;
-};
-
-__device__ __forceinline__ TabVal table_interp(const float4* __restrict__ T, int nlg, const TabRow& rw,
-                                               const TabCol& cl) {
-    const float4* t = T + (rw.j0 * nlg + cl.i0);
-    const float4 a = t[0];        // row j0
-    const float4 b = t[nlg];      // row j0 + 1
-    const float fa = fmaf(rw.wj, b.x - a.x, a.x);      // F at i0
-    const float fc = fmaf(rw.wj, b.y - a.y, a.y);      // F at i0 + 1
-    const float na = fmaf(rw.wj, b.z - a.z, a.z);
-    const float nc = fmaf(rw.wj, b.w - a.w, a.w);
-    TabVal v;
-    v.slopeF = fc - fa;
-    v.F = fmaf(cl.wi, fc - fa, fa);
-    v.N = fmaf(cl.wi, nc - na, na);
-    return v;
+// one gather per row brings both columns of a quantity.  tb is the line's table,
+// tb1 = tb + nlg * 16 bytes (row j0 + 1 at the same offset).
+template <int HALF>      // 0: F, 1: Ndot
+__device__ __forceinline__ float2 table_pair(const char* __restrict__ tb, const char* __restrict__ tb1,
+                                             const TabRow& rw, const TabCol& cl, float& slope) {
+    const uint32_t o = (uint32_t)rw.off + ((uint32_t)cl.i0 << 4) + 8u * HALF;
+    const float2 a = *reinterpret_cast<const float2*>(tb + o);      // row j0
+    const float2 b = *reinterpret_cast<const float2*>(tb1 + o);     // row j0 + 1
+    const float fa = fmaf(rw.wj, b.x - a.x, a.x);                    // at column i0
+    const float fc = fmaf(rw.wj, b.y - a.y, a.y);                    // at column i0 + 1
+    slope = fc - fa;
+    return make_float2(fa, fc);
 }
 
-// Table rows of a particle for both signs of u.
-struct TabRows {
-    TabRow pos, neg;
-};
-
-__device__ __forceinline__ TabRows table_rows(const LineDev& L, int ns, double x) {
-    TabRows r;
-    r.pos = table_row(L, ns, x);
-    r.neg = table_row(L, ns, (double)L.n_cells - x);
-    return r;
-}
-
-template <bool DF>
-__device__ __forceinline__ float table_F(const LineDev& L, const float4* __restrict__ tab, int nlg, const TabRows& rows,
-                                         float u, float& dF) {
-    const float ua = fabsf(u);
-    const TabCol cl = table_col(L, nlg, ua);
-    const TabVal v = table_interp(tab, nlg, u < 0.0f ? rows.neg : rows.pos, cl);
-    if (DF) {
-        // d(fractional index)/d|u| = (nlg-1)/8 |u| / (gamma^2 ln 10); for u < 0,
-        // d(-F(|u|))/du = +dF/d|u|
-        dF = cl.inside ? v.slopeF * (float)L.lg_scale * ua * frcp(fmaf(ua, ua, 1.0f) * 2.302585093f) : 0.0f;
+// F_hat from the table at u, with what dF/du needs (the slope per column).
+struct TableEval {
+    float F, slope, ua, g2;
+    bool inside;
+    // d(fractional column)/d|u| = (nlg-1)/8 |u| / (gamma^2 ln 10); for u < 0,
+    // d(-F(|u|))/du = +dF/d|u|
+    __device__ __forceinline__ float dF(const LineDev& L) const {
+        return inside ? slope * (float)L.lg_scale * ua * frcp(g2 * 2.302585093f) : 0.0f;
     }
-    return u < 0.0f ? -v.F : v.F;
+};
+
+__device__ __forceinline__ TableEval table_eval(const LineDev& L, const char* tb, const char* tb1, int nlg,
+                                                const TabRows& rows, float u) {
+    TableEval e;
+    e.ua = fabsf(u);
+    const TabCol cl = table_col(L, nlg, e.ua);
+    const float2 f = table_pair<0>(tb, tb1, u < 0.0f ? rows.neg : rows.pos, cl, e.slope);
+    const float F = fmaf(cl.wi, e.slope, f.x);
+    e.F = u < 0.0f ? -F : F;
+    e.g2 = cl.g2;
+    e.inside = cl.inside;
+    return e;
 }
 
-__device__ __forceinline__ float table_N(const LineDev& L, const float4* __restrict__ tab, int nlg,
+__device__ __forceinline__ float table_N(const LineDev& L, const char* tb, const char* tb1, int nlg,
                                          const TabRows& rows, float u) {
     const TabCol cl = table_col(L, nlg, fabsf(u));
-    return table_interp(tab, nlg, u < 0.0f ? rows.neg : rows.pos, cl).N;
+    float slope;
+    const float2 n = table_pair<1>(tb, tb1, u < 0.0f ? rows.neg : rows.pos, cl, slope);
+    return fmaf(cl.wi, slope, n.x);
 }
 
 __device__ __forceinline__ float photon_energy(float gam, float b) {

@@ -86,6 +86,8 @@ const char* validate_config(const pic1d_config* c) {
     if (c->rics_backend < 0 || c->rics_backend > 3) return "unknown rics_backend";
     if (c->rics_backend == 2 && (c->table_nlg < 2 || c->table_ns < 2 || c->table_nlg > 4096 || c->table_ns > 65536))
         return "table dimensions out of range";
+    if (c->rics_backend == 2 && (int64_t)c->table_nlg * c->table_ns > (1ll << 27))
+        return "table_nlg * table_ns must not exceed 2^27";
     if (c->conversion != 0 && c->conversion != 1) return "unknown conversion mode";
     if (c->sort_interval < 0) return "sort_interval must be >= 0";
     int64_t cells = 0;
@@ -138,8 +140,9 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
     d.b_thr = (float)c->b_thr;
     d.s_scale = c->rics_backend == 2 ? (double)c->table_ns / n : 0.0;
     d.lg_scale = c->rics_backend == 2 ? (c->table_nlg - 1) / 8.0 : 0.0;
+    d.s_scale_f = (float)d.s_scale;
     {
-        const double k = d.lg_scale * log10(2.0);
+        const double k = 0.5 * d.lg_scale * log10(2.0);
         const double k_hi = floor(k * 1024.0) / 1024.0;
         d.lgk = (float)k;
         d.lgk_hi = (float)k_hi;
