@@ -686,13 +686,15 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
         // three cells packed in 10-bit fields of hc
         int key = cc.cell;
         int jv0 = 0, jv1 = 0, jv2 = 0, hc = 0;
-        auto flush_run = [&]() {
+        // flush the lowest `ncells` cells of the run's three (all of them, or only
+        // key-1 when the next run starts in key+1 and the other two carry over)
+        auto flush_run = [&](int ncells) {
             const int jv[3] = {jv0, jv1, jv2};
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const int cell = key - 1 + r;
                 const int hv = (hc >> (10 * r)) & 1023;
-                if (cell >= 0 && cell < L.n_cells) {
+                if (r < ncells && cell >= 0 && cell < L.n_cells) {
                     const long long j = (long long)(T.negative ? -jv[r] : jv[r]) << POS_TO_FIX;
                     if (use_lds) {
                         if (j != 0) atomicAdd(&sJ[wid][cell - lo], (unsigned long long)j);
@@ -703,7 +705,6 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
                     }
                 }
             }
-            jv0 = jv1 = jv2 = hc = 0;
         };
 #pragma unroll 1
         for (int q = 0; q < PUSH_PPT; ++q) {
@@ -711,7 +712,17 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
             const int c0 = sPc[wid][slot][lane];
             const bool alive = c0 != DEAD_CELL;
             if (alive && c0 != cc.cell) {
-                flush_run();
+                if (c0 == key + 1) {
+                    // slide the run one cell up: key and key+1 carry over
+                    flush_run(1);
+                    jv0 = jv1;
+                    jv1 = jv2;
+                    jv2 = 0;
+                    hc >>= 10;
+                } else {
+                    flush_run(3);
+                    jv0 = jv1 = jv2 = hc = 0;
+                }
                 cache_load<BACKEND>(cc, a, L, qmC, c0);
                 key = c0;
             }
@@ -731,7 +742,7 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
             sPo[wid][slot][lane] = gone ? 0.5f : o1;
             sPu[wid][slot][lane] = gone ? 0.0f : uq;
         }
-        flush_run();
+        flush_run(3);
         // write back (vector stores for full groups; never touch slots >= ncur, where
         // appended particles may be landing)
         if (nv == PUSH_PPT) {
