@@ -93,7 +93,8 @@ enum { PIC1D_CNT_EVENTS = 0,          /* stochastic RICS events                 
 
 typedef struct {
     double r_eq;              /* equatorial radius of the line, R_max / R*   */
-    int32_t n_cells;          /* cells, uniform in arc length (>= 2)         */
+    int32_t n_cells;          /* cells, uniform in arc length, 2..2^26; at   */
+                              /*   most 2^27 cells over all lines            */
     int32_t ppc_init;         /* initial e-/e+ pairs per cell (>= 0)         */
     int32_t init_mode;        /* PIC1D_INIT_*                                */
     int32_t pad0;

@@ -40,6 +40,7 @@ struct Layout {
     int64_t table_floats = 0;
     int32_t n_layer = 0;
     int32_t photon_region = 0;   // photon records per append region
+    int32_t n_chunks = 0;        // chunks of SCAN_CELLS cells over all lines (the sort's scan)
     bool mlp = false;            // surrogate-network RICS backend
 };
 
@@ -70,7 +71,9 @@ struct pic1d_state {
     float* E32 = nullptr;
     unsigned long long* J = nullptr;
     int32_t* hist[2] = {nullptr, nullptr};
-    int32_t *pair_step = nullptr, *pair_last = nullptr, *cursor = nullptr, *cell_line = nullptr;
+    int32_t *pair_step = nullptr, *pair_last = nullptr, *cell_line = nullptr;
+    int4 *bins = nullptr, *chunk_sum = nullptr;
+    int32_t *chunk_line = nullptr, *line_chunk0 = nullptr;
     long long *pair_sum = nullptr, *n_sum = nullptr, *avg_count = nullptr;
     float4* nodes = nullptr;
     double* rc_nodes = nullptr;
@@ -155,6 +158,7 @@ Layout plan_layout(const pic1d_config* c, std::vector<LineHost>* lines_out) {
         LineHost lh;
         build_line(c, l, cb, (int32_t)(toff / 4), lh);
         cb += c->lines[l].n_cells;
+        L.n_chunks += (c->lines[l].n_cells + SCAN_CELLS - 1) / SCAN_CELLS;
         L.max_nodes = std::max(L.max_nodes, c->lines[l].n_cells + 1);
         for (int s = 0; s < 4; ++s) L.total_slots += lh.cap[s];
         toff += (int64_t)lh.table.size();
@@ -196,7 +200,10 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->j_sum = cv.take<double>(L.n_cells);
     s->hist[0] = cv.take<int32_t>(4 * (size_t)L.n_cells);
     s->hist[1] = cv.take<int32_t>(4 * (size_t)L.n_cells);
-    s->cursor = cv.take<int32_t>(4 * (size_t)L.n_cells);
+    s->bins = cv.take<int4>((size_t)SORT_SUB * L.n_cells);
+    s->chunk_sum = cv.take<int4>(L.n_chunks);
+    s->chunk_line = cv.take<int32_t>(L.n_chunks);
+    s->line_chunk0 = cv.take<int32_t>(L.n_lines + 1);
     s->pair_step = cv.take<int32_t>(L.n_cells);
     s->pair_last = cv.take<int32_t>(L.n_cells);
     s->cell_line = cv.take<int32_t>(L.n_cells);
@@ -323,9 +330,15 @@ int launch_sort(pic1d_state* st) {
     s.seg_base = st->seg_base; s.seg_cap = st->seg_cap; s.n_cur = st->n_cur; s.alloc = st->alloc;
     s.tile_prefix = st->tile_prefix;
     s.nseg = st->lay.nseg; s.lines = st->dlines; s.hist[0] = st->hist[0]; s.hist[1] = st->hist[1];
-    s.cursor = st->cursor; s.new_count = st->new_count; s.sc = st->sc;
+    s.bins = st->bins; s.chunk_sum = st->chunk_sum; s.chunk_line = st->chunk_line; s.line_chunk0 = st->line_chunk0;
+    s.n_chunks = st->lay.n_chunks; s.n_bins = SORT_SUB * st->lay.n_cells;
+    s.new_count = st->new_count; s.sc = st->sc;
     const int pk = prof_begin(st, 4);
-    hipLaunchKernelGGL(k_sort_scan, dim3(st->lay.nseg), dim3(1024), 0, st->stream, s);
+    hipLaunchKernelGGL(k_sort_zero, dim3(st->aux_blocks), dim3(256), 0, st->stream, s);
+    hipLaunchKernelGGL(k_sort_count, dim3(4 * st->aux_blocks), dim3(PUSH_TPB), 0, st->stream, s);
+    hipLaunchKernelGGL(k_sort_chunks, dim3(st->lay.n_chunks), dim3(SCAN_CELLS), 0, st->stream, s);
+    hipLaunchKernelGGL(k_sort_lines, dim3(st->lay.n_lines), dim3(256), 0, st->stream, s);
+    hipLaunchKernelGGL(k_sort_cursors, dim3(st->lay.n_chunks), dim3(SCAN_CELLS), 0, st->stream, s);
     hipLaunchKernelGGL(k_sort_scatter, dim3(4 * st->aux_blocks), dim3(PUSH_TPB), 0, st->stream, s);
     hipLaunchKernelGGL(k_sort_finish, dim3((st->lay.nseg + 255) / 256), dim3(256), 0, st->stream, s);
     prof_end(st, pk);
@@ -436,7 +449,7 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     std::vector<float> nodes;
     std::vector<double> rcn;
     std::vector<float> table;
-    std::vector<int32_t> lc, ll, lt, cell_line;
+    std::vector<int32_t> lc, ll, lt, cell_line, chunk_line, line_chunk0;
     for (int l = 0; l < st->lay.n_lines; ++l) {
         const LineHost& lh = st->lines[l];
         ld[l] = lh.dev;
@@ -449,7 +462,10 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
             lt.push_back(lh.layer_target[k]);
         }
         cell_line.insert(cell_line.end(), lh.dev.n_cells, l);
+        line_chunk0.push_back((int32_t)chunk_line.size());
+        chunk_line.insert(chunk_line.end(), (lh.dev.n_cells + SCAN_CELLS - 1) / SCAN_CELLS, l);
     }
+    line_chunk0.push_back((int32_t)chunk_line.size());
     INIT_TRY(hipMemcpyAsync(st->seg_base, st->seg_base_h.data(), nseg * sizeof(int64_t), hipMemcpyHostToDevice, s));
     INIT_TRY(hipMemcpyAsync(st->seg_cap, st->seg_cap_h.data(), nseg * sizeof(int32_t), hipMemcpyHostToDevice, s));
     INIT_TRY(hipMemcpyAsync(st->dlines, ld.data(), ld.size() * sizeof(LineDev), hipMemcpyHostToDevice, s));
@@ -463,6 +479,9 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
         INIT_TRY(hipMemcpyAsync(st->layer_target, lt.data(), lt.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     }
     INIT_TRY(hipMemcpyAsync(st->cell_line, cell_line.data(), cell_line.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(st->chunk_line, chunk_line.data(), chunk_line.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(st->line_chunk0, line_chunk0.data(), line_chunk0.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
     if (st->lay.mlp) {
         for (int k = 0; k < 6; ++k) st->mlp_norm[k] = cfg->mlp_norm[k];
         for (int l = 0; l < st->lay.n_lines; ++l) {
@@ -498,6 +517,8 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     INIT_TRY(hipMemcpyAsync(st->alloc, alloc0.data(), nseg * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (launch_plan(st, 0) != PIC1D_OK) return bail(PIC1D_EDEVICE, st->err);
     if (launch_hist(st) != PIC1D_OK) return bail(PIC1D_EDEVICE, st->err);
+    // the initial plasma in position order (its offsets are random within each cell)
+    if (cfg->sort_interval > 0 && launch_sort(st) != PIC1D_OK) return bail(PIC1D_EDEVICE, st->err);
     INIT_TRY(hipStreamSynchronize(s));
     INIT_TRY(hipGetLastError());
 #undef INIT_TRY

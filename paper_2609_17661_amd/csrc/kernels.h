@@ -15,6 +15,8 @@ constexpr int PUSH_PPT = 8;                     // consecutive particles per thr
 constexpr int CNT_REPL = 64;                    // replicas of every counter (spreads same-address atomics)
 constexpr int PUSH_TILE = 64 * PUSH_PPT;        // particles per tile: one wavefront's work item
 constexpr int AUX_PPT = PUSH_TILE / PUSH_TPB;   // particles per thread when a block takes a tile
+constexpr int SORT_SUB = 8;                     // sort key: cell and offset in eighths of a cell
+constexpr int SCAN_CELLS = 256;                 // cells per chunk of the sort's scan (one block)
 
 constexpr int PHOTON_REPL = 64;                 // append regions of the photon buffer
 
@@ -155,7 +157,12 @@ struct SortArgs {
     int32_t nseg;
     const LineDev* lines;
     int32_t* hist[2];          // counts per cell and species; current = hist[step & 1]
-    int32_t* cursor;           // [cells][4]
+    int4* bins;                // [cells * SORT_SUB]: counts, then cursors, per species
+    int4* chunk_sum;           // [n_chunks]: counts per chunk, then its first slot per species
+    const int32_t* chunk_line; // [n_chunks]: line of each chunk of SCAN_CELLS cells
+    const int32_t* line_chunk0;// [n_lines + 1]: first chunk of each line
+    int32_t n_chunks;
+    int32_t n_bins;            // cells * SORT_SUB
     int32_t* new_count;        // [nseg]
     DevScalars* sc;
 };
@@ -208,7 +215,11 @@ __global__ void k_atmosphere(AtmArgs a);
 __global__ void k_convert(ConvertArgs a);
 __global__ void k_plan(BookArgs b, int advance_step);
 __global__ void k_field(FieldArgs f);
-__global__ void k_sort_scan(SortArgs s);
+__global__ void k_sort_zero(SortArgs s);
+__global__ void k_sort_count(SortArgs s);
+__global__ void k_sort_chunks(SortArgs s);
+__global__ void k_sort_lines(SortArgs s);
+__global__ void k_sort_cursors(SortArgs s);
 __global__ void k_sort_scatter(SortArgs s);
 __global__ void k_sort_finish(SortArgs s);
 __global__ void k_init_pairs(InitArgs a);

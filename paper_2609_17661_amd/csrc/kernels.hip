@@ -5,10 +5,10 @@
 //                 deposit (LDS window per tile), per-cell histogram of the new
 //                 positions, pair injection by append
 //   k_atmosphere  refill of the surface layers by append
-//   k_field       Ampere E -= 4 pi (j - j_twist), averages, per-step bookkeeping
-//                 (counts, tile plan, step counter)
-//   k_sort_*      every sort_interval steps: counting sort by cell per segment,
-//                 dropping absorbed particles
+//   k_field       Ampere E -= 4 pi (j - j_twist), averages
+//   k_plan        live counts, tile plan of the next push, step counter
+//   k_sort_*      every sort_interval steps: counting sort by position (cell and
+//                 eighth of a cell) per segment, dropping absorbed particles
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -1033,40 +1033,160 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f) {
 }
 
 // ---------------------------------------------------------------------------
-// Sort by cell (counting sort per segment), dropping absorbed particles.
-// k_sort_scan: one block per segment, exclusive scan of the per-cell counts of
-// that species into cursor[cell][species]; also the new live count.
+// Sort by position (counting sort per segment on the key cell * SORT_SUB +
+// floor(offset * SORT_SUB)), dropping absorbed particles.  Ordering by eighths
+// of a cell, not only by cell, keeps a lane's consecutive particles together in
+// space, so that after a step the ones that crossed a face are grouped instead
+// of spread through every lane's slots.  Counts live in bins[cell * SORT_SUB +
+// sub] as one int4 (the four species):
+//   k_sort_zero     clears the bins
+//   k_sort_count    counts the live particles per bin
+//   k_sort_chunks   per chunk of SCAN_CELLS cells: its counts
+//   k_sort_lines    per line: exclusive scan over its chunks, and the new counts
+//   k_sort_cursors  per chunk: each bin's first slot
+//   k_sort_scatter  every particle takes the next slot of its bin
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_sort_scan(SortArgs s) {
-    __shared__ long long sPart[1024];
-    if (s.sc->err != 0) return;
-    const int seg = blockIdx.x;
-    const int line = seg >> 2, sp = seg & 3;
-    const LineDev& L = s.lines[line];
-    const int n = L.n_cells;
-    const int per = (n + 1023) / 1024;
-    const int c0 = threadIdx.x * per;
-    const int32_t* hist = s.hist[s.sc->step & 1];
-    long long sum = 0;
-    for (int c = c0; c < min(c0 + per, n); ++c) sum += hist[4 * (size_t)(L.cell_base + c) + sp];
-    sPart[threadIdx.x] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const long long v = (threadIdx.x >= o) ? sPart[threadIdx.x - o] : 0;
-        __syncthreads();
-        sPart[threadIdx.x] += v;
-        __syncthreads();
-    }
-    long long run = sPart[threadIdx.x] - sum;
-    for (int c = c0; c < min(c0 + per, n); ++c) {
-        s.cursor[4 * (size_t)(L.cell_base + c) + sp] = (int)run;
-        run += hist[4 * (size_t)(L.cell_base + c) + sp];
-    }
-    if (threadIdx.x == 1023) s.new_count[seg] = (int)sPart[1023];
+__device__ __forceinline__ int sort_bin(int cell_base, int c, float off) {
+    return (cell_base + c) * SORT_SUB + min((int)(off * (float)SORT_SUB), SORT_SUB - 1);
 }
 
-// k_sort_scatter: every live particle takes the next slot of its cell; lanes of a
-// wavefront that share a cell reserve their slots with one atomic.
+__device__ __forceinline__ int& int4_at(int4& v, int k) {
+    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
+}
+
+// For each lane: the lanes of the wavefront (among `active`) with the same key, and
+// the lowest of them.
+__device__ __forceinline__ unsigned long long match_key(int key, bool active, int& leader) {
+    unsigned long long act = __ballot(active), mine = 0ull;
+    leader = 0;
+    while (act) {
+        const int l = __ffsll((long long)act) - 1;
+        const int k = __shfl(key, l, 64);
+        const unsigned long long m = __ballot(active && key == k);
+        if (active && key == k) {
+            mine = m;
+            leader = l;
+        }
+        act &= ~m;
+    }
+    return mine;
+}
+
+__global__ __launch_bounds__(256) void k_sort_zero(SortArgs s) {
+    if (s.sc->err != 0) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s.n_bins; i += gridDim.x * blockDim.x)
+        s.bins[i] = make_int4(0, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void k_sort_count(SortArgs s) {
+    if (s.sc->err != 0) return;
+    const int total = s.tile_prefix[s.nseg];
+    const int lane = threadIdx.x & 63;
+    for (TileWalk tw(total); tw.t < tw.end; tw.t += tw.stride) {
+        const int t = tw.t;
+        const int seg = find_segment(s.tile_prefix, s.nseg, t);
+        const int sp = seg & 3;
+        const LineDev& L = s.lines[seg >> 2];
+        const int ncur = s.n_cur[seg];
+        const int64_t base = s.seg_base[seg];
+        const int i0 = (t - s.tile_prefix[seg]) * PUSH_TILE;
+        for (int q = 0; q < AUX_PPT; ++q) {
+            const int i = i0 + q * PUSH_TPB + threadIdx.x;
+            const int c = (i < ncur) ? s.cell[base + i] : DEAD_CELL;
+            const bool live = c != DEAD_CELL;
+            const int bin = live ? sort_bin(L.cell_base, c, s.off[base + i]) : 0;
+            int leader;
+            const unsigned long long m = match_key(bin, live, leader);
+            if (live && lane == leader) atomicAdd(&int4_at(s.bins[bin], sp), __popcll(m));
+        }
+    }
+}
+
+// Block-wide exclusive scan of one int4 per thread (256 threads); returns the
+// thread's prefix and writes the block total.
+__device__ __forceinline__ int4 block_scan_int4(int4 v, int4& total) {
+    __shared__ int4 sPart[256];
+    const int t = threadIdx.x;
+    sPart[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int4 w = t >= o ? sPart[t - o] : make_int4(0, 0, 0, 0);
+        __syncthreads();
+        if (t >= o) sPart[t] = make_int4(sPart[t].x + w.x, sPart[t].y + w.y, sPart[t].z + w.z, sPart[t].w + w.w);
+        __syncthreads();
+    }
+    const int4 inc = sPart[t];
+    total = sPart[255];
+    __syncthreads();
+    return make_int4(inc.x - v.x, inc.y - v.y, inc.z - v.z, inc.w - v.w);
+}
+
+// Counts of one cell (thread) of a chunk (block), summed over its bins.
+__device__ __forceinline__ int4 cell_counts(const SortArgs& s, int chunk, int& gcell, bool& in) {
+    const int line = s.chunk_line[chunk];
+    const LineDev& L = s.lines[line];
+    const int c = (chunk - s.line_chunk0[line]) * SCAN_CELLS + (int)threadIdx.x;
+    in = c < L.n_cells;
+    gcell = L.cell_base + c;
+    int4 n = make_int4(0, 0, 0, 0);
+    if (in) {
+#pragma unroll
+        for (int k = 0; k < SORT_SUB; ++k) {
+            const int4 b = s.bins[gcell * SORT_SUB + k];
+            n.x += b.x; n.y += b.y; n.z += b.z; n.w += b.w;
+        }
+    }
+    return n;
+}
+
+__global__ __launch_bounds__(256) void k_sort_chunks(SortArgs s) {
+    if (s.sc->err != 0) return;
+    int gcell;
+    bool in;
+    const int4 n = cell_counts(s, blockIdx.x, gcell, in);
+    int4 total;
+    (void)block_scan_int4(n, total);
+    if (threadIdx.x == 0) s.chunk_sum[blockIdx.x] = total;
+}
+
+// One block per line: the chunks' first slots (exclusive scan over the line's
+// chunks, per species) and the line's new live counts.
+__global__ __launch_bounds__(256) void k_sort_lines(SortArgs s) {
+    if (s.sc->err != 0) return;
+    const int line = blockIdx.x;
+    const int c0 = s.line_chunk0[line], c1 = s.line_chunk0[line + 1];
+    int4 run = make_int4(0, 0, 0, 0);
+    for (int b = c0; b < c1; b += 256) {
+        const int k = b + (int)threadIdx.x;
+        const int4 v = k < c1 ? s.chunk_sum[k] : make_int4(0, 0, 0, 0);
+        int4 total;
+        const int4 ex = block_scan_int4(v, total);
+        if (k < c1) s.chunk_sum[k] = make_int4(run.x + ex.x, run.y + ex.y, run.z + ex.z, run.w + ex.w);
+        run = make_int4(run.x + total.x, run.y + total.y, run.z + total.z, run.w + total.w);
+    }
+    if (threadIdx.x < 4) s.new_count[4 * line + threadIdx.x] = int4_at(run, threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_sort_cursors(SortArgs s) {
+    if (s.sc->err != 0) return;
+    int gcell;
+    bool in;
+    const int4 n = cell_counts(s, blockIdx.x, gcell, in);
+    int4 total;
+    const int4 ex = block_scan_int4(n, total);
+    if (!in) return;
+    const int4 c0 = s.chunk_sum[blockIdx.x];
+    int4 run = make_int4(c0.x + ex.x, c0.y + ex.y, c0.z + ex.z, c0.w + ex.w);
+#pragma unroll
+    for (int k = 0; k < SORT_SUB; ++k) {
+        const int4 b = s.bins[gcell * SORT_SUB + k];
+        s.bins[gcell * SORT_SUB + k] = run;
+        run = make_int4(run.x + b.x, run.y + b.y, run.z + b.z, run.w + b.w);
+    }
+}
+
+// Every live particle takes the next slot of its bin: the lanes of a wavefront
+// that share a bin reserve their slots with one atomic, all bins at once.
 __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs s) {
     if (s.sc->err != 0) return;
     const int total = s.tile_prefix[s.nseg];
@@ -1083,38 +1203,31 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs s) {
         for (int q = 0; q < AUX_PPT; ++q) {
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
             const int c = (i < ncur) ? s.cell[base + i] : DEAD_CELL;
-            bool pending = (c != DEAD_CELL);
-            // the particle's other fields are read while its slot is being reserved
+            const bool live = c != DEAD_CELL;
             float pof = 0.0f, puv = 0.0f;
             uint64_t pid = 0;
-            if (pending) {
+            if (live) {
                 pof = s.off[base + i];
                 puv = s.u[base + i];
                 pid = s.id[base + i];
             }
-            int pos = 0;
-            unsigned long long act = __ballot(pending);
-            while (act) {
-                const int leader = __ffsll((long long)act) - 1;
-                const int cl = __shfl(c, leader, 64);
-                const unsigned long long m = __ballot(pending && c == cl);
-                int basepos = 0;
-                if (lane == leader) basepos = atomicAdd(&s.cursor[4 * (size_t)(L.cell_base + cl) + sp], __popcll(m));
-                basepos = __shfl(basepos, leader, 64);
-                if (pending && c == cl) {
-                    pos = basepos + __popcll(m & ((1ull << lane) - 1ull));
-                    pending = false;
-                    if (pos < cap) {
-                        const int64_t dst = base + pos;
-                        s.cell2[dst] = c;
-                        s.off2[dst] = pof;
-                        s.u2[dst] = puv;
-                        s.id2[dst] = pid;
-                    } else {
-                        set_error(&s.sc->err, -3);
-                    }
+            const int bin = live ? sort_bin(L.cell_base, c, pof) : 0;
+            int leader;
+            const unsigned long long m = match_key(bin, live, leader);
+            int first = 0;
+            if (live && lane == leader) first = atomicAdd(&int4_at(s.bins[bin], sp), __popcll(m));
+            first = __shfl(first, leader, 64);
+            if (live) {
+                const int pos = first + __popcll(m & ((1ull << lane) - 1ull));
+                if (pos < cap) {
+                    const int64_t dst = base + pos;
+                    s.cell2[dst] = c;
+                    s.off2[dst] = pof;
+                    s.u2[dst] = puv;
+                    s.id2[dst] = pid;
+                } else {
+                    set_error(&s.sc->err, -3);
                 }
-                act &= ~m;
             }
         }
     }

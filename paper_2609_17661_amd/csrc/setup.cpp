@@ -104,7 +104,7 @@ const char* validate_config(const pic1d_config* c) {
             if (ln.capacity[s] < 0 || ln.capacity[s] >= (1ll << 31)) return "capacity per species must be < 2^31";
         cells += ln.n_cells;
     }
-    if (cells >= (1ll << 30)) return "too many cells in total";
+    if (cells > (1ll << 27)) return "too many cells in total (at most 2^27)";
     return "";
 }
 
