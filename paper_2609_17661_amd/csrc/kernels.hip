@@ -630,13 +630,25 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
         else stage(std::false_type{});
         const bool lane_any = hi_s >= 0;
         const int first = lane_any ? (int)lo_u : 0;
+        // the first cell's cache, loaded early so that its latency hides under the
+        // tile set-up below
+        const float qmC = ((sp == 0 || sp == 2) ? -1.0f : (sp == 1 ? 1.0f : a.qm_ion)) * L.invC;
+        CellCache cc;
+        cache_load<BACKEND>(cc, a, L, qmC, first);
         // The order in which the lane visits its slots: by cell (dead slots last), so
         // that the run accumulator and the cell cache see each cell once however the
         // particles of a cell are ordered in memory.  A 19-comparator sorting network
         // on keys (cell - first) * 8 + slot; the slot order is packed in 3-bit fields.
+        // Slots already in that order (as unsigned, DEAD_CELL is the largest) keep
+        // it; the network runs when any lane of the wavefront needs it.
         static_assert(PUSH_PPT == 8, "the visit order packs 8 slots in 3-bit fields");
-        uint32_t visit = 0;
-        {
+        constexpr uint32_t IN_ORDER = 0u | 1u << 3 | 2u << 6 | 3u << 9 | 4u << 12 | 5u << 15 | 6u << 18 | 7u << 21;
+        uint32_t visit = IN_ORDER;
+        bool ordered = true;
+#pragma unroll
+        for (int q = 1; q < PUSH_PPT; ++q) ordered = ordered && (uint32_t)cst[q] >= (uint32_t)cst[q - 1];
+        if (__ballot(!ordered) != 0ull) {
+            visit = 0;
             uint32_t k[PUSH_PPT];
 #pragma unroll
             for (int q = 0; q < PUSH_PPT; ++q)
@@ -652,9 +664,17 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
 #pragma unroll
             for (int q = 0; q < PUSH_PPT; ++q) visit |= (k[q] & 7u) << (3 * q);
         }
-        // window [lo, hi] of cells this wavefront's deposit can touch
-        int lo = wave_min_i(lane_any ? (int)lo_u - 1 : INT32_MAX);
-        int hi = wave_max_i(lane_any ? hi_s + 1 : INT32_MIN);
+        // window [lo, hi] of cells this wavefront's deposit can touch: in a tile in
+        // position order, the first lane's lowest and the last lane's highest cell;
+        // checked, and reduced over the wavefront where that guess fails
+        const int lane_lo = lane_any ? (int)lo_u - 1 : INT32_MAX;
+        const int lane_hi = lane_any ? hi_s + 1 : INT32_MIN;
+        int lo = __builtin_amdgcn_readfirstlane(lane_lo);
+        int hi = __builtin_amdgcn_readlane(lane_hi, 63);
+        if (__ballot(lane_lo < lo || lane_hi > hi) != 0ull) {
+            lo = wave_min_i(lane_lo);
+            hi = wave_max_i(lane_hi);
+        }
         const bool any = lo <= hi;
         lo = any ? max(lo, 0) : 0;
         hi = any ? min(hi, L.n_cells - 1) : -1;
@@ -675,12 +695,8 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
         T.inv_mass = (sp == 3) ? a.inv_mass_ion : 1.0f;
         T.gravity = a.gravity && any && ((double)lo <= L.atm_depth + 1.0 ||
                                          (double)(L.n_cells - 1 - hi) <= L.atm_depth + 1.0);
-        const float qmC = T.qm * L.invC;
         unsigned long long* Jg = a.J + L.cell_base;
         int* Hg = hist_out + 4 * (size_t)L.cell_base + sp;
-
-        CellCache cc;
-        cache_load<BACKEND>(cc, a, L, qmC, first);
         // per-lane run accumulator over consecutive particles of one cell: deposits
         // (2^-28 cell) into cells key-1, key, key+1 and the new-cell counts of the same
         // three cells packed in 10-bit fields of hc
