@@ -217,8 +217,9 @@ int pic1d_set_step(pic1d_state* st, int64_t step);
  * and records an event pair around every kernel that pic1d_step launches from
  * then on; pic1d_profile(st, 0) stops.  pic1d_profile_read fills out->ms[k]
  * (total milliseconds) and out->launches[k] for k = PIC1D_KERNEL_*. */
-enum { PIC1D_KERNEL_PUSH = 0, PIC1D_KERNEL_ATMOSPHERE = 1, PIC1D_KERNEL_FIELD = 2, PIC1D_KERNEL_PLAN = 3,
-       PIC1D_KERNEL_SORT = 4, PIC1D_KERNEL_CONVERT = 5, PIC1D_NKERNELS = 8 };
+enum { PIC1D_KERNEL_PUSH = 0,
+       PIC1D_KERNEL_APPEND = 1,   /* pair conversion and atmosphere refill (one launch) */
+       PIC1D_KERNEL_FIELD = 2, PIC1D_KERNEL_PLAN = 3, PIC1D_KERNEL_SORT = 4, PIC1D_NKERNELS = 8 };
 typedef struct {
     double ms[8];
     int64_t launches[8];

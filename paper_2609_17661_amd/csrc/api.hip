@@ -538,9 +538,12 @@ int enqueue_step(pic1d_state* st) {
     {
         int rc = launch_push(st);
         if (rc) return rc;
+        // pair conversion and atmosphere refill, one launch
+        ConvertArgs ca{};
+        AtmArgs aa{};
+        int conv_blocks = 0, atm_blocks = 0;
+        const int b = st->cur;
         if (st->cfg.pairs) {
-            ConvertArgs ca{};
-            const int b = st->cur;
             ca.cell = st->cell[b]; ca.off = st->off[b]; ca.u = st->u[b]; ca.id = st->id[b];
             ca.seg_base = st->seg_base; ca.seg_cap = st->seg_cap; ca.alloc = st->alloc; ca.lines = st->dlines;
             ca.rc_nodes = st->rc_nodes; ca.hist[0] = st->hist[0]; ca.hist[1] = st->hist[1];
@@ -548,24 +551,24 @@ int enqueue_step(pic1d_state* st) {
             ca.photons = st->photons; ca.n_photons = st->n_photons; ca.photon_region = st->lay.photon_region;
             ca.conversion = st->cfg.conversion;
             ca.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); ca.key1 = (uint32_t)(st->cfg.seed >> 32);
-            const int pk = prof_begin(st, 5);
-            hipLaunchKernelGGL(k_convert, dim3(st->aux_blocks), dim3(256), 0, st->stream, ca);
-            prof_end(st, pk);
+            conv_blocks = st->aux_blocks;
         }
+        ca.sc = st->sc;
         if (st->cfg.atmosphere && st->lay.n_layer > 0) {
-            AtmArgs a{};
-            const int b = st->cur;
-            a.cell = st->cell[b]; a.off = st->off[b]; a.u = st->u[b]; a.id = st->id[b];
-            a.seg_base = st->seg_base; a.seg_cap = st->seg_cap; a.alloc = st->alloc; a.lines = st->dlines;
-            a.hist[0] = st->hist[0]; a.hist[1] = st->hist[1];
-            a.layer_cell = st->layer_cell; a.layer_line = st->layer_line; a.layer_target = st->layer_target;
-            a.n_layer = st->lay.n_layer; a.counters = st->counters; a.sc = st->sc;
-            a.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); a.key1 = (uint32_t)(st->cfg.seed >> 32);
-            a.sig_e = (float)sqrt(st->cfg.atm_T);
-            a.sig_i = (float)sqrt(st->cfg.atm_T / st->cfg.mass_ratio);
-            const int blocks = std::min(st->aux_blocks, (st->lay.n_layer * 64 + 255) / 256);
+            aa.cell = st->cell[b]; aa.off = st->off[b]; aa.u = st->u[b]; aa.id = st->id[b];
+            aa.seg_base = st->seg_base; aa.seg_cap = st->seg_cap; aa.alloc = st->alloc; aa.lines = st->dlines;
+            aa.hist[0] = st->hist[0]; aa.hist[1] = st->hist[1];
+            aa.layer_cell = st->layer_cell; aa.layer_line = st->layer_line; aa.layer_target = st->layer_target;
+            aa.n_layer = st->lay.n_layer; aa.counters = st->counters; aa.sc = st->sc;
+            aa.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); aa.key1 = (uint32_t)(st->cfg.seed >> 32);
+            aa.sig_e = (float)sqrt(st->cfg.atm_T);
+            aa.sig_i = (float)sqrt(st->cfg.atm_T / st->cfg.mass_ratio);
+            atm_blocks = std::max(1, std::min(st->aux_blocks, (st->lay.n_layer * 64 + 255) / 256));
+        }
+        if (conv_blocks + atm_blocks > 0) {
             const int pk = prof_begin(st, 1);
-            hipLaunchKernelGGL(k_atmosphere, dim3(std::max(blocks, 1)), dim3(256), 0, st->stream, a);
+            hipLaunchKernelGGL(k_append, dim3(conv_blocks + atm_blocks), dim3(256), 0, st->stream, ca, aa,
+                               conv_blocks);
             prof_end(st, pk);
         }
         f.E = st->E; f.E32 = st->E32; f.J = st->J; f.j_last = st->j_last; f.hist[0] = st->hist[0]; f.hist[1] = st->hist[1];
@@ -573,10 +576,11 @@ int enqueue_step(pic1d_state* st) {
         f.pair_sum = st->pair_sum; f.n_sum = st->n_sum; f.avg_count = st->avg_count; f.cell_line = st->cell_line;
         f.lines = st->dlines; f.n_total = nt; f.frozen = st->cfg.frozen_field; f.avg_start = st->cfg.avg_start_step;
         f.sc = st->sc;
+        // Ampere; its block 0 also plans the next push and advances the step counter
         const int pk = prof_begin(st, 2);
-        hipLaunchKernelGGL(k_field, dim3(std::min(st->aux_blocks, (nt + 255) / 256)), dim3(256), 0, st->stream, f);
+        hipLaunchKernelGGL(k_field, dim3(std::min(st->aux_blocks, (nt + 255) / 256)), dim3(256), 0, st->stream, f,
+                           book_args(st));
         prof_end(st, pk);
-        launch_plan(st, 1);
         st->host_step += 1;
         if (st->cfg.sort_interval > 0 && st->host_step % st->cfg.sort_interval == 0) {
             rc = launch_sort(st);

@@ -211,10 +211,9 @@ template <int BACKEND> __global__ void k_push(PushArgs a);
 __global__ void k_mlp_pack(const float* p, bf16x8* ft, bf16x8* bt, float* bias);
 __global__ void k_rics_eval_mlp(PushArgs a, int line, int64_t n, const float* s_cells, const float* u, float* F,
                                 float* N, float* eps);
-__global__ void k_atmosphere(AtmArgs a);
-__global__ void k_convert(ConvertArgs a);
+__global__ void k_append(ConvertArgs ca, AtmArgs aa, int conv_blocks);
 __global__ void k_plan(BookArgs b, int advance_step);
-__global__ void k_field(FieldArgs f);
+__global__ void k_field(FieldArgs f, BookArgs b);
 __global__ void k_sort_zero(SortArgs s);
 __global__ void k_sort_count(SortArgs s);
 __global__ void k_sort_chunks(SortArgs s);

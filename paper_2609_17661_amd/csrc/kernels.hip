@@ -4,7 +4,8 @@
 //   k_push        gather, RICS drag / events, kick, move, fixed-point current
 //                 deposit (LDS window per tile), per-cell histogram of the new
 //                 positions, pair injection by append
-//   k_atmosphere  refill of the surface layers by append
+//   k_append      photon conversion into pairs and refill of the surface
+//                 layers, both by append
 //   k_field       Ampere E -= 4 pi (j - j_twist), averages
 //   k_plan        live counts, tile plan of the next push, step counter
 //   k_sort_*      every sort_interval steps: counting sort by position (cell and
@@ -542,6 +543,7 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
     }
     if (a.sc->err != 0) return;
     const uint64_t step = a.sc->step;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->step_field = step;
     const int32_t* hist_in = (step & 1) ? a.hist[1] : a.hist[0];
     int32_t* hist_out = (step & 1) ? a.hist[0] : a.hist[1];
     const int total = a.tile_prefix[a.nseg];
@@ -814,14 +816,13 @@ template __global__ void k_push<RICS_MLP>(PushArgs);
 // The whole grid walks the photon records of all regions, one wavefront per 64
 // consecutive records.  Appends and counters are aggregated per wavefront and
 // line: one atomic per (wave, line) on each allocation counter and counter slot.
-__global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
-    if (a.sc->err != 0) return;
+__device__ __forceinline__ void convert_photons(const ConvertArgs& a, int blk, int nblk) {
     const uint64_t step = a.sc->step;
     const int32_t* hist_in = (step & 1) ? a.hist[1] : a.hist[0];
     int32_t* hist_out = (step & 1) ? a.hist[0] : a.hist[1];
     const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwave = (gridDim.x * blockDim.x) >> 6;
+    const int wave = (blk * blockDim.x + threadIdx.x) >> 6;
+    const int nwave = (nblk * blockDim.x) >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     // region fills, one per lane (PHOTON_REPL == 64), read once per wavefront
     static_assert(PHOTON_REPL == 64, "one photon region per lane");
@@ -921,13 +922,12 @@ __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
 // Atmosphere (Appendix B.1): every layer cell is refilled to its hydrostatic
 // target with co-located (e-, ion) pairs; one wavefront per layer cell.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_atmosphere(AtmArgs a) {
-    if (a.sc->err != 0) return;
+__device__ __forceinline__ void refill_atmosphere(const AtmArgs& a, int blk, int nblk) {
     const uint64_t step = a.sc->step;
     int32_t* hist_out = a.hist[(step & 1) ^ 1];
     const int lane = threadIdx.x & 63;
-    const int wglob = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nw = (gridDim.x * blockDim.x) >> 6;
+    const int wglob = (blk * blockDim.x + threadIdx.x) >> 6;
+    const int nw = (nblk * blockDim.x) >> 6;
     for (int e = wglob; e < a.n_layer; e += nw) {
         const int g = a.layer_cell[e];         // global cell
         const int line = a.layer_line[e];
@@ -965,10 +965,20 @@ __global__ __launch_bounds__(256) void k_atmosphere(AtmArgs a) {
         if (lane == 0) {
             h[2] += D;
             h[3] += D;
-            atomicAdd(&a.counters[((size_t)line * CNT_REPL + (blockIdx.x & (CNT_REPL - 1))) * NCOUNT + 7],
+            atomicAdd(&a.counters[((size_t)line * CNT_REPL + (blk & (CNT_REPL - 1))) * NCOUNT + 7],
                       (unsigned long long)D);
         }
     }
+}
+
+// The step's appends in one launch: blocks [0, conv_blocks) convert the recorded
+// photons into pairs (species 0 and 1), the rest refill the atmosphere (species 2
+// and 3).  The two touch different segments and different species counts, so they
+// run side by side.
+__global__ __launch_bounds__(256) void k_append(ConvertArgs ca, AtmArgs aa, int conv_blocks) {
+    if (ca.sc->err != 0) return;
+    if ((int)blockIdx.x < conv_blocks) convert_photons(ca, blockIdx.x, conv_blocks);
+    else refill_atmosphere(aa, blockIdx.x - conv_blocks, gridDim.x - conv_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1012,14 +1022,21 @@ __global__ __launch_bounds__(256) void k_plan(BookArgs b, int advance_step) {
 }
 
 // Ampere's law with the static twist current (Sec. 3): E -= 4 pi (j - j_twist),
-// plus time averages and the reset of the step's accumulators.
-__global__ __launch_bounds__(256) void k_field(FieldArgs f) {
+// plus time averages and the reset of the step's accumulators.  Block 0 also does
+// the step's bookkeeping (live counts, the next push's tile plan) and advances the
+// step counter; the cells read the running step from the copy the push left.
+__global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
     if (f.sc->err != 0) return;
+    if (blockIdx.x == 0) {
+        bookkeeping(b);
+        if (threadIdx.x == 0 && b.sc->err == 0) b.sc->step += 1;
+    }
+    const uint64_t step = f.sc->step_field;
     const int n = f.n_total;
-    const int hin = (int)(f.sc->step & 1);
+    const int hin = (int)(step & 1);
     int* hist_in = f.hist[hin];
     const int* hist_out = f.hist[hin ^ 1];
-    const bool averaging = f.avg_start >= 0 && f.sc->step >= (uint64_t)f.avg_start;
+    const bool averaging = f.avg_start >= 0 && step >= (uint64_t)f.avg_start;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
         const int line = f.cell_line[g];
         const LineDev& L = f.lines[line];

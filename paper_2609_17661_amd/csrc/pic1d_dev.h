@@ -69,6 +69,7 @@ struct DevScalars {
     uint64_t step;        // steps taken; keys Philox
     int32_t err;          // first error code (pic1d_status), 0 if none
     int32_t pad;
+    uint64_t step_field;  // the running step, as k_field reads it (k_field advances `step`)
 };
 
 // ---------------------------------------------------------------------------

@@ -63,7 +63,7 @@ class CProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
 
 
-KERNELS = ("push", "atmosphere", "field", "plan", "sort", "convert")
+KERNELS = ("push", "append", "field", "plan", "sort")
 
 
 class CTuneOut(ctypes.Structure):
