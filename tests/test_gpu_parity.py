@@ -161,6 +161,34 @@ def test_result_independent_of_sorting_and_bitwise_reproducible():
     np.testing.assert_array_equal(Ea, Ec)
 
 
+def test_sort_orders_particles_by_position():
+    """After a sort every species array is in position order by eighths of a cell
+    (cell * 8 + floor(8 * offset) nondecreasing), absorbed particles are gone, and
+    the set of particles is unchanged."""
+    cfg = workloads.small(n_cells=300, ppc=20, rics="exact", init="hot", gamma_max=1e3, pairs=True,
+                          atmosphere=True, sort_interval=5)
+    sim = _sim(cfg)
+    first = [sim.get_particles(0, s) for s in range(4)]
+    for P in first:                    # the initial plasma is sorted once after init
+        key = P["cell"].astype(np.int64) * 8 + np.minimum((P["off"] * 8).astype(np.int64), 7)
+        assert np.all(np.diff(key) >= 0)
+    sim.step(4)
+    before = [sim.get_particles(0, s) for s in range(4)]
+    sim.step(1)                        # step 5: push, appends, then the sort
+    after = [sim.get_particles(0, s) for s in range(4)]
+    unsorted = 0
+    for P in before:
+        key = P["cell"].astype(np.int64) * 8 + np.minimum((P["off"] * 8).astype(np.int64), 7)
+        unsorted += int(np.sum(np.diff(key) < 0))
+    assert unsorted > 0                # four pushes of a hot plasma do disorder it
+    for P in after:
+        key = P["cell"].astype(np.int64) * 8 + np.minimum((P["off"] * 8).astype(np.int64), 7)
+        assert np.all(np.diff(key) >= 0)
+        assert len(np.unique(P["id"])) == len(P["id"])
+    m = sim.moments(0)
+    assert [len(P["id"]) for P in after] == list(m["count"])
+
+
 def test_capacity_overflow_freezes_state():
     cfg = workloads.small(n_cells=64, ppc=8, rics="exact", pairs=True)
     cfg["lines"][0]["capacity"] = [64 * 8 + 5, 64 * 8 + 5, 64, 64]
