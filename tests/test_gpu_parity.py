@@ -63,6 +63,12 @@ CASES = {
                                         capacity=[300_000, 300_000, 1000, 1000])]),
     "exact-r30-sorted": workloads.small(r_eq=30.0, n_cells=300, ppc=8, rics="exact", pairs=True,
                                         conversion="curvature", atmosphere=True, sort_interval=2),
+    # the drag-time and mass-ratio variants of the paper's parameter studies: a ten
+    # times shorter tau_min (more particles on the damping branch), and ions at the
+    # physical mass ratio in the atmosphere
+    "exact-eta100": workloads.small(rics="exact", pairs=True, eta_min=100.0),
+    "table-mass1836-atmosphere": workloads.small(n_cells=160, ppc=8, init="cold", rics="table", table_nlg=64,
+                                                 table_ns=96, atmosphere=True, mass_ratio=1836.15),
 }
 
 
