@@ -6,6 +6,7 @@ timed on the host as a CPU baseline.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--backend table|exact|off]
                     [--workload cfg2|cfg1] [--no-cpu-baseline] [--no-surrogate]
     python bench.py --copy-calibration     # plain 256 MiB device copy, for HBM counters
+    python bench.py --cascade              # the combined cascade run (cfg5) on its own
 
 Plain path (the headline `value`): the R_max = 30 line with 65,536 cells, 200
 e-/e+ per cell each (2.6e7 particles), surface atmosphere with ions at
@@ -25,6 +26,11 @@ library (outside the timed region), then the R_max = 4 line of its training
 geometry at the same particle count (65,536 cells x 200 hot e-/e+ per cell) is
 stepped with the TABLE, EXACT and MLP backends in turn.  The network's error is
 judged against the library's EXACT backend at the workload's particles.
+
+Cascade run (`--cascade`, not part of the default line): 64 lines of 32,768
+cells whose hot pair seed cascades up to n_max (about 4e8 particles), stepped
+from 100-step graphs in chunks; wall time, particle count and pair multiplicity
+per chunk, and k_push's HBM rate at the final count.
 
 Inputs are synthetic (Philox initial plasma) and resident in HBM before each
 timed region.  One JSON line is printed.
@@ -275,6 +281,52 @@ def batched_path(steps, warmup):
     return out
 
 
+def cascade_run(chunks, chunk_steps, profile_steps):
+    """The combined cascade run (cfg5): 64 lines of 32,768 cells whose hot pair seed
+    cascades up to n_max, stepped in chunks replayed from graphs; wall time, particle
+    count and pair multiplicity per chunk, then a profiled window for k_push's HBM
+    rate at the final particle count."""
+    import torch
+
+    from paper_2609_17661_amd import Pic1D, workloads
+
+    def live(sim):
+        return sum(sum(sim.moments(li)["count"]) for li in range(sim.n_lines))
+
+    t0 = time.perf_counter()
+    cfg = workloads.cfg5()
+    sim = Pic1D(cfg, device="cuda:0")
+    t_init = time.perf_counter() - t0
+    seed_pairs = sum(l["ppc_init"] * l["n_cells"] for l in cfg["lines"])
+    n_start = live(sim)
+    sim.set_graph(100)
+    rows, pairs, wall = [], 0, 0.0
+    for c in range(chunks):
+        r = timed_run(sim, chunk_steps, 0, profile=False)
+        pairs += r["counters"]["pairs_created"]
+        wall += r["ms"] * 1e-3
+        rows.append({"steps_done": (c + 1) * chunk_steps, "ms_per_step": r["ms_per_step"],
+                     "particle_steps_per_s": r["value"], "particles": live(sim), "pairs_created": pairs})
+        print(f"# cascade chunk {c}: {rows[-1]}", file=sys.stderr, flush=True)
+    rp = timed_run(sim, profile_steps, 0, profile=True)
+    bytes_per_launch = hbm_bytes_per_launch(rp)
+    gauss = max(sim.moments(li)["gauss_residual"] for li in range(sim.n_lines))
+    out = {"workload": f"cfg5: {sim.n_lines} lines, R_max log-uniform in [10, 100], 32768 cells each, hot pair "
+                       f"seed {cfg['lines'][0]['ppc_init']} e-/e+ per cell (gamma to 1e4), n_max = 6 n0 (n0 = 32), atmosphere with ions at "
+                       f"m_i/m_e = 100, pairs (curvature), TABLE RICS, 100-step graphs",
+           "init_seconds": t_init, "wall_seconds": wall, "steps": chunks * chunk_steps,
+           "particles_start": n_start, "particles_end": rows[-1]["particles"],
+           "pair_multiplicity": pairs / seed_pairs, "chunks": rows,
+           "k_push_ms_at_end": rp["push_avg_s"] * 1e3,
+           "hbm_GBps_at_end": bytes_per_launch / rp["push_avg_s"] / 1e9,
+           "roofline_frac_at_end": bytes_per_launch / rp["push_avg_s"] / HBM_PEAK,
+           "gauss_residual_max_over_lines": gauss}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +344,9 @@ def main():
     ap.add_argument("--surrogate-steps", type=int, default=10)
     ap.add_argument("--mlp-train-steps", type=int, default=200000)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--cascade", action="store_true",
+                    help="only the combined cascade run (cfg5), as its own JSON line")
+    ap.add_argument("--cascade-chunks", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures the hot path on one GPU only (requested --gpus {args.gpus}); "
@@ -305,6 +360,9 @@ def main():
 
     from paper_2609_17661_amd import Pic1D, workloads
 
+    if args.cascade:
+        print(json.dumps({"cascade": cascade_run(args.cascade_chunks, 100, 20)}), flush=True)
+        return
     if args.surrogate_only:
         print(json.dumps({"surrogate_vs_table": surrogate_comparison(args.surrogate_steps, 3, args.mlp_train_steps)}),
               flush=True)

@@ -24,6 +24,11 @@ at the sizes of the benchmark configurations:
             R_max through those endpoints, rounded to multiples of 256),
             32-256 e-/e+ per cell per line (uniform integers), cold start,
             TABLE RICS, pairs on with curvature conversion.
+* cfg5()    the combined cascade run: 64 lines with R_max log-uniform in
+            [10, 100], 32,768 cells each, a hot pair seed of 64 e-/e+ per cell
+            cascading up to n_max = 6 n0 (n0 = 32 per cell: about 4e8
+            particles over all lines), the surface atmosphere with ions at
+            m_i/m_e = 100, pairs on with curvature conversion, TABLE RICS.
 """
 import numpy as np
 
@@ -67,6 +72,23 @@ def cfg3(n_lines=256, seed=0, rics="table", headroom=1.05):
         lines.append(dict(r_eq=float(r), n_cells=int(n), ppc_init=int(p), init="cold", capacity=[cap, cap, 0, 0]))
     return dict(rics=rics, table_nlg=256, table_ns=512, kT_keV=0.5, j_twist=0.5, ppc0=float(np.mean(ppc)),
                 pairs=True, conversion="curvature", seed=seed, sort_interval=50, lines=lines)
+
+
+def cfg5(n_lines=64, seed=0, rics="table", n_cells=32768, ppc=64, nmax_over_n0=6.0, ppc0=32.0):
+    """The combined cascade run: 64 lines with R_max log-uniform in [10, 100], 32,768
+    cells each, a hot pair seed (gamma log-uniform to 1e4) cascading up to
+    n_max = nmax_over_n0 * ppc0 particles per cell (about 4e8 over all lines), the
+    surface atmosphere with ions at m_i/m_e = 100, pairs with curvature conversion."""
+    rng = np.random.default_rng(seed)
+    R = 10.0 * 10.0 ** rng.random(n_lines)
+    nmax = nmax_over_n0 * ppc0
+    cap_pair = int(0.6 * nmax * n_cells) + ppc * n_cells + 4096
+    cap_atm = 16 * n_cells
+    lines = [dict(r_eq=float(r), n_cells=n_cells, ppc_init=ppc, init="hot", init_gamma_max=1.0e4,
+                  capacity=[cap_pair, cap_pair, cap_atm, cap_atm]) for r in R]
+    return dict(rics=rics, table_nlg=256, table_ns=512, kT_keV=0.5, j_twist=0.5, ppc0=ppc0, pairs=True,
+                conversion="curvature", nmax_over_n0=nmax_over_n0, atmosphere=True, mass_ratio=100.0,
+                seed=seed, sort_interval=50, lines=lines)
 
 
 def small(r_eq=4.0, n_cells=96, ppc=16, init="hot", **kw):
