@@ -137,6 +137,24 @@ def _child_ids(ocfg, step, parent_ids):
     return ids
 
 
+def _child_parent_x(ocfg, step, parts_before):
+    """Position before the step of the parent of every pair member that a lepton of
+    parts_before could create this step (child id -> parent x)."""
+    k0, k1 = philox.seed_key(ocfg["seed"])
+    out = {}
+    for s in (0, 1):
+        P = parts_before[s]
+        if P["id"].size == 0:
+            continue
+        lo, hi = philox.split_id(P["id"].astype(np.uint64))
+        w = philox.philox4x32_10(step, lo, hi, philox.STREAM_CHILD, k0, k1)
+        x = P["cell"].astype(np.float64) + P["off"].astype(np.float64)
+        for a, b in ((0, 1), (2, 3)):
+            for cid, xp in zip(philox.id_from_words(w[a], w[b]), x):
+                out[int(cid)] = float(xp)
+    return out
+
+
 def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=None):
     """Advance the oracle from snap_before and compare with the GPU's snap_after.
 
@@ -152,6 +170,7 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
         marg, scattered = _marginal_parents(ocfg, before, li)
         excused_new = _child_ids(ocfg, before.step, marg)
         atm_cells_excused = set()
+        parent_x = None
         maxcount = 1
         for s in range(4):
             G = Lg["parts"][s]
@@ -180,8 +199,14 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
             raw_cell = cg != co
             bad_cell = raw_cell & ~near_edge & ~exc
             tolx = np.where(is_new, xtol_new if xtol_new is not None else xtol, xtol)
-            if ocfg["conversion"] == "curvature":
-                tolx = np.where(is_new, np.maximum(tolx, 1e-5 * np.abs(xo) + xtol), tolx)
+            if ocfg["conversion"] == "curvature" and is_new.any():
+                # a pair member sits at the parent's position plus R_curv arcsin(2/eps),
+                # computed from the parent's float32 state: its error scales with that
+                # distance (and with the distance from the wall, for the rounding of x)
+                if parent_x is None:
+                    parent_x = _child_parent_x(ocfg, snap_before["step"], snap_before["lines"][li]["parts"])
+                dist = np.array([abs(x - parent_x.get(int(i), x)) for i, x in zip(common, xo)])
+                tolx = np.where(is_new, np.maximum(tolx, 1e-5 * (np.abs(xo) + dist) + xtol), tolx)
             dx = np.abs(xg - xo)
             raw_x = dx > tolx
             bad_x = raw_x & ~exc

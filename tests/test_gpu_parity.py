@@ -69,6 +69,11 @@ CASES = {
     "exact-eta100": workloads.small(rics="exact", pairs=True, eta_min=100.0),
     "table-mass1836-atmosphere": workloads.small(n_cells=160, ppc=8, init="cold", rics="table", table_nlg=64,
                                                  table_ns=96, atmosphere=True, mass_ratio=1836.15),
+    # fewer table rows than cells (as in the benchmark lines): most cells take their
+    # row positions from the per-cell cache, the cells that straddle a row the
+    # float64 form
+    "table-rows-per-cell": workloads.small(n_cells=400, ppc=6, rics="table", table_nlg=96, table_ns=37,
+                                           pairs=True, conversion="curvature"),
 }
 
 
