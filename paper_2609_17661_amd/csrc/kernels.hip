@@ -36,8 +36,21 @@ __device__ __forceinline__ int wave_sum_i(int v) {
     return v;
 }
 
+// Data that the running kernel never writes (segment tables, line constants),
+// read at a wave-uniform index: through the constant address space the compiler
+// issues scalar loads into SGPRs instead of holding the values in VGPRs.
+template <typename T>
+__device__ __forceinline__ auto kconst(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (const __attribute__((address_space(4))) T*)(p);
+#else
+    return p;
+#endif
+}
+
 // Segment of a global tile index by binary search over the tile prefix.
-__device__ __forceinline__ int find_segment(const int32_t* __restrict__ prefix, int nseg, int t) {
+template <typename P>
+__device__ __forceinline__ int find_segment(P prefix, int nseg, int t) {
     int lo = 0, hi = nseg;           // prefix[lo] <= t < prefix[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -508,7 +521,17 @@ __device__ __forceinline__ void counts_flush(unsigned long long* counters, int l
     c = Counts();
 }
 
-constexpr int WW = 256;     // deposit window of one wavefront, cells
+// Deposit window of one wavefront (cells) and waves per SIMD of the particle
+// kernel, per backend.  A wavefront's LDS is its staged tile (6 KB) plus the
+// window (12 bytes per cell): with 128 cells five 256-thread blocks fit a CU
+// (five waves per SIMD, what the table backend's registers allow), with 32 cells
+// six (the closed-form and field-only backends, in 80 registers with at most a
+// few spilled).  Tiles whose
+// cells span more than the window deposit through global atomics instead.
+constexpr int push_ww(int backend) { return backend == RICS_TABLE ? 128 : 32; }
+constexpr int push_waves(int backend) {
+    return backend == RICS_MLP ? 1 : backend == RICS_TABLE ? 5 : 6;
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -525,7 +548,8 @@ __device__ __forceinline__ void wave_sync() {
 // synchronisation.
 template <int BACKEND>
 __global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB)
-__attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(PushArgs a) {
+__attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a) {
+    constexpr int WW = push_ww(BACKEND);
     constexpr int TPB = BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB;
     __shared__ unsigned long long sJ[TPB / 64][WW];
     __shared__ int sH[TPB / 64][WW];
@@ -565,16 +589,16 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
     auto fetch = [&](int t) {
         const bool have = t < ww.end;
         if (have && (t < seg_t0 || t >= seg_t1)) {
-            seg = find_segment(a.tile_prefix, a.nseg, t);
-            seg_t0 = a.tile_prefix[seg];
-            seg_t1 = a.tile_prefix[seg + 1];
+            seg = find_segment(kconst(a.tile_prefix), a.nseg, t);
+            seg_t0 = kconst(a.tile_prefix)[seg];
+            seg_t1 = kconst(a.tile_prefix)[seg + 1];
         }
         f_seg = seg;
-        f_base = a.seg_base[seg];
+        f_base = kconst(a.seg_base)[seg];
         // this lane's PUSH_PPT consecutive particles (vector loads; slots up to the
         // capacity, a multiple of 256, always exist)
         const int t0 = (t - seg_t0) * PUSH_TILE;
-        const int ncur = a.n_cur[seg];
+        const int ncur = kconst(a.n_cur)[seg];
         f_full = have && ncur - t0 >= PUSH_TILE;        // wave-uniform
         f_ib = t0 + lane * PUSH_PPT;
         f_nv = have ? max(0, min(PUSH_PPT, ncur - f_ib)) : 0;
@@ -598,7 +622,7 @@ __attribute__((amdgpu_waves_per_eu(BACKEND == RICS_MLP ? 1 : 4))) void k_push(Pu
             if (cur_line >= 0) counts_flush(a.counters, cur_line, cnt);
             cur_line = line;
         }
-        const LineDev L = a.lines[line];
+        const LineDev L = kconst(a.lines)[line];
         // the fetched particles, staged in the wave's LDS slots [q][lane] so the
         // particle loop indexes them freely without bank conflicts.  Dead slots are
         // stored as (DEAD_CELL, 1/2, 0); the padding of a partial tile is made so.
