@@ -31,9 +31,12 @@ def _steps_match(sim, cfg, n=3):
     return total
 
 
+@pytest.mark.parametrize("n", [64, 200])
 @pytest.mark.parametrize("rics", ["exact", "table"])
-def test_extreme_particles_step_parity(rics):
-    n = 64
+def test_extreme_particles_step_parity(rics, n):
+    # one tile holds every particle, so its cells span the whole line: wider than
+    # the per-wave deposit window of the closed-form backend at 64 cells and of
+    # both backends at 200 cells (the deposit then goes through global atomics)
     cfg = workloads.small(r_eq=4.0, n_cells=n, ppc=1, init="empty", rics=rics, pairs=True, table_nlg=256,
                           table_ns=256, capacity=[100_000, 100_000, 0, 0])
     sim = Pic1D(cfg)
@@ -45,7 +48,7 @@ def test_extreme_particles_step_parity(rics):
     for s in (0, 1):
         ids = (np.arange(C.size, dtype=np.uint64) * np.uint64(2) + np.uint64(s))
         sim.set_particles(0, s, C, O, U, ids)
-    _print(rics, "particles per species", C.size)
+    _print(rics, n, "cells, particles per species", C.size)
     total = _steps_match(sim, cfg)
     assert total["compared"] > 0
     # by construction 3 of the 5 offsets (0, 1e-7, 1 - 2^-24) with |u| <= 1e-30 keep
