@@ -28,6 +28,7 @@ STREAM_CHILD = 3      # ids of the pair created by a converting photon
 STREAM_ATM_A = 4      # atmosphere: position and electron momentum
 STREAM_ATM_B = 5      # atmosphere: ion momentum
 STREAM_ATM_ID = 6     # atmosphere: ids of the injected electron and ion
+STREAM_ANNIH = 7      # pair annihilation: ranking key of every e-/e+ in a cell over n_max
 
 HASHED_ID_BIT = np.uint64(1) << np.uint64(63)
 

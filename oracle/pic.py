@@ -36,10 +36,13 @@ post-kick momentum, recoil, move -- is a reading, the paper being silent):
      count of all particles in that cell is below n_max;
   8. atmosphere: refill the layer cells to the hydrostatic profile with
      co-located (e-, ion) pairs;
-  9. Ampere  E_{k+1/2} -= 4 pi (j_{k+1/2} - j_psi).
+  9. pair annihilation at the density limit n_max (see `annihilate`);
+ 10. Ampere  E_{k+1/2} -= 4 pi (j_{k+1/2} - j_psi).
 
 Pins: tests/test_oracle_pic.py (hyperbolic motion, Gauss's law to roundoff,
-energy ledger with drag off, cold two-stream growth rate).  The atmosphere
+energy ledger with drag off, cold two-stream growth rate) and
+tests/test_oracle_annihilation.py (the current of one annihilated pair in closed
+form, Gauss's law, the count left in a cell, independence of the particle order).  The atmosphere
 and pair-yield statistics are "parity unpinned" beyond Gauss neutrality and
 agreement with the GPU path; the event kinematics choice is pinned only by the
 photon-energy identities of rics.py.
@@ -65,6 +68,7 @@ DEFAULTS = dict(
     table_ns=512, pairs=False, conversion="immediate", nmax_over_n0=0.0,
     atmosphere=False, atm_a0=0.0, atm_h_cells=0.0, atm_T=0.01, atm_cut=0.01,
     gravity=True, frozen_field=False, seed=0, lines=None, mlp_params=None, mlp_norm=None,
+    annihilation=True,
 )
 
 
@@ -186,7 +190,7 @@ def _empty():
 
 
 COUNTER_NAMES = ('events', 'pairs_created', 'photons_escaped', 'absorbed',
-                 'psc_clipped', 'limited', 'newton_unconverged', 'atm_injected')
+                 'psc_clipped', 'limited', 'newton_unconverged', 'atm_injected', 'annihilated')
 
 
 def _zero_counters():
@@ -270,6 +274,63 @@ def cell_counts(ln, parts, species=None, use_key='x'):
         if xc.size:
             tot += np.bincount(np.floor(xc).astype(np.int64), minlength=n)
     return tot
+
+
+def annihilation_keys(step, ids, k0, k1):
+    """64-bit ranking keys of the annihilation draw: words 1 (high) and 0 (low) of
+    the Philox block (step, id low, id high, STREAM_ANNIH)."""
+    lo, hi = philox.split_id(ids)
+    w = philox.philox4x32_10(step, lo, hi, philox.STREAM_ANNIH, k0, k1)
+    return (w[1].astype(np.uint64) << np.uint64(32)) | w[0].astype(np.uint64)
+
+
+def annihilate(ln, parts, nstep, k0, k1, j, counters):
+    """Pair annihilation at the density limit (Sec. 3: pairs annihilate where the
+    total density approaches n_max, so that the skin depth stays resolved; the
+    paper gives no mechanics, so these are readings):
+
+      * a cell whose count N of all particles (after the step's push, pair
+        creation and atmosphere refill) exceeds n_max loses
+        k = min(N-, N+, ceil((N - n_max)/2)) secondary pairs, N-/N+ its e-/e+
+        (species 0/1) counts; atmospheric electrons and ions do not annihilate;
+      * the annihilating e- and e+ are the k of each species in the cell with the
+        smallest (key, id), key = `annihilation_keys` -- a choice independent of
+        where the particles sit in memory;
+      * charge conservation: each pair annihilates as if its positron first moved
+        to its electron, which deposits +Q (x- - x+) on the cell's face current;
+        summed over the cell's pairs that is Q (sum x- - sum x+), whatever the
+        pairing, and the neutral pair then leaves no charge behind.
+
+    Returns the new per-species particle dicts; adds the current to j.
+    """
+    n = ln.n
+    counts = cell_counts(ln, parts)
+    over = counts > ln.n_max
+    if not over.any():
+        return parts
+    ne = cell_counts(ln, parts, species=(0,))
+    npos = cell_counts(ln, parts, species=(1,))
+    need = np.ceil((counts - ln.n_max) / 2.0)
+    k = np.where(over, np.minimum(np.minimum(ne, npos), need), 0).astype(np.int64)
+    out = list(parts)
+    xsum = []
+    for s in (0, 1):
+        P = parts[s]
+        if P['x'].size == 0:
+            xsum.append(np.zeros(n))
+            continue
+        cell = np.floor(P['x']).astype(np.int64)
+        key = annihilation_keys(nstep, P['id'], k0, k1)
+        order = np.lexsort((P['id'], key, cell))       # by cell, then key, then id
+        cs = cell[order]
+        rank = np.arange(cs.size) - np.searchsorted(cs, cs, side='left')
+        remove = np.zeros(cs.size, dtype=bool)
+        remove[order] = rank < k[cs]
+        xsum.append(np.bincount(cell[remove], weights=P['x'][remove], minlength=n))
+        out[s] = dict(x=P['x'][~remove], u=P['u'][~remove], id=P['id'][~remove])
+    j += ln.Q * (xsum[0] - xsum[1])
+    counters['annihilated'] += int(k.sum())
+    return out
 
 
 def step(st, stats=None):
@@ -414,6 +475,9 @@ def _step_line(st, li, stats):
                 new_parts[s] = dict(x=np.concatenate([P['x'], xa]), u=np.concatenate([P['u'], uu]),
                                     id=np.concatenate([P['id'], ids]))
             cnt['atm_injected'] += int(cc.size)
+
+    if cfg['annihilation']:
+        new_parts = annihilate(ln, new_parts, nstep, k0, k1, j, cnt)
 
     st.parts[li] = new_parts
     st.j_last[li] = j
