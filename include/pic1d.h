@@ -89,6 +89,7 @@ enum { PIC1D_CNT_EVENTS = 0,          /* stochastic RICS events                 
        PIC1D_CNT_PUSHED = 8,          /* particle-steps pushed                  */
        PIC1D_CNT_DRAWS = 9,           /* Philox draws of event decisions        */
        PIC1D_CNT_MLP_EVALS = 10,      /* surrogate-network evaluations (one per lane and call) */
+       PIC1D_CNT_ANNIHILATED = 11,    /* e-/e+ pairs annihilated at the density limit */
        PIC1D_NCOUNTERS = 16 };
 
 typedef struct {
@@ -125,6 +126,9 @@ typedef struct {
     int32_t atmosphere;       /* 1: refill the surface layers (Appendix B.1) */
     int32_t gravity;          /* 1: gravity T/h towards the wall in the layer */
     int32_t frozen_field;     /* 1: skip Ampere (test mode)                  */
+    int32_t annihilation;     /* 1: e-/e+ pairs annihilate in cells over n_max
+                               *   (Sec. 3): see pic1d_step                   */
+    int32_t pad1;
     double nmax_over_n0;      /* n_max/n0 per cell, all species; <= 0: d0_cells^2 */
     double atm_a0;            /* peak atmosphere density / n0; <= 0: 18 |j_twist| */
     double atm_h_cells;       /* scale height in cells; <= 0: 3 d0 / a0^(1/2) */
@@ -153,7 +157,7 @@ typedef struct {
     double energy_kinetic;    /* sum m c^2 (gamma - 1), code units            */
     double energy_field;      /* sum E^2 / 8 pi, code units                   */
     int64_t count[4];         /* live particles per species                   */
-    int64_t counters[16];     /* PIC1D_CNT_* since init (slots 11-15 reserved) */
+    int64_t counters[16];     /* PIC1D_CNT_* since init (slots 12-15 reserved) */
     int64_t step;             /* steps taken since init                       */
     int64_t avg_steps;        /* steps in the averages                        */
 } pic1d_moments_out;
@@ -175,6 +179,16 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out);
 /* Advance all lines by n_steps >= 0 steps; enqueues the work and returns after
  * checking the device error word of the completed steps (this synchronises
  * the stream once per call).
+ *
+ * One step (Sec. 3): gather, RICS drag / events, kick, move, charge-conserving
+ * deposit; photon conversion into pairs; atmosphere refill; with
+ * cfg->annihilation, pair annihilation at the density limit; Ampere.  The
+ * annihilation reading (the paper gives no mechanics): a cell holding N > n_max
+ * particles of all species after the step's appends loses
+ * k = min(N-, N+, ceil((N - n_max)/2)) e-/e+ pairs of species 0/1, those with
+ * the smallest 64-bit Philox keys (step, id, stream 7), ties by id; the cell's
+ * face current gains Q (sum x- - sum x+), as if each positron moved to its
+ * electron before the neutral pair vanished, so Gauss's law holds.
  * Errors: ECAPACITY, ENONFINITE (state frozen), ESTATE, EDEVICE. */
 int pic1d_step(pic1d_state* st, int32_t n_steps);
 
@@ -219,7 +233,9 @@ int pic1d_set_step(pic1d_state* st, int64_t step);
  * (total milliseconds) and out->launches[k] for k = PIC1D_KERNEL_*. */
 enum { PIC1D_KERNEL_PUSH = 0,
        PIC1D_KERNEL_APPEND = 1,   /* pair conversion and atmosphere refill (one launch) */
-       PIC1D_KERNEL_FIELD = 2, PIC1D_KERNEL_PLAN = 3, PIC1D_KERNEL_SORT = 4, PIC1D_NKERNELS = 8 };
+       PIC1D_KERNEL_FIELD = 2, PIC1D_KERNEL_PLAN = 3, PIC1D_KERNEL_SORT = 4,
+       PIC1D_KERNEL_ANNIHILATE = 5,   /* annihilation plan and candidates (two launches) */
+       PIC1D_NKERNELS = 8 };
 typedef struct {
     double ms[8];
     int64_t launches[8];

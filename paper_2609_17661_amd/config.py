@@ -34,6 +34,7 @@ DEFAULTS = dict(
     atm_cut=0.01,
     gravity=True,
     frozen_field=False,
+    annihilation=True,  # e-/e+ pairs annihilate in cells over n_max (Sec. 3)
     seed=0,
     sort_interval=0,
     avg_start_step=-1,

@@ -78,6 +78,7 @@ struct pic1d_state {
     float4* nodes = nullptr;
     double* rc_nodes = nullptr;
     float4* table = nullptr;
+    int32_t *ann_k = nullptr, *ann_off = nullptr, *ann_fill = nullptr, *ann_ctl = nullptr;
     int32_t *layer_cell = nullptr, *layer_line = nullptr, *layer_target = nullptr;
     unsigned long long* counters = nullptr;
     DevScalars* sc = nullptr;
@@ -213,6 +214,10 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->nodes = cv.take<float4>(L.n_nodes);
     s->rc_nodes = cv.take<double>(L.n_nodes);
     s->table = cv.take<float4>(std::max<int64_t>(L.table_floats / 4, 1));
+    s->ann_k = cv.take<int32_t>(L.n_cells);
+    s->ann_off = cv.take<int32_t>(L.n_cells);
+    s->ann_fill = cv.take<int32_t>(2 * (size_t)L.n_cells);
+    s->ann_ctl = cv.take<int32_t>(4);
     s->layer_cell = cv.take<int32_t>(std::max(L.n_layer, 1));
     s->layer_line = cv.take<int32_t>(std::max(L.n_layer, 1));
     s->layer_target = cv.take<int32_t>(std::max(L.n_layer, 1));
@@ -352,8 +357,9 @@ int check_error(pic1d_state* st) {
     HIP_TRY(st, hipStreamSynchronize(st->stream));
     if (h.err != 0) {
         st->frozen = h.err;
-        return fail(st, h.err, h.err == PIC1D_ECAPACITY ? "particle capacity exceeded (state frozen)"
-                                                         : "non-finite momentum (state frozen)");
+        return fail(st, h.err, h.err == PIC1D_ECAPACITY   ? "particle capacity exceeded (state frozen)"
+                               : h.err == PIC1D_ENONFINITE ? "non-finite momentum (state frozen)"
+                                                           : "cell counts and particles disagree (state frozen)");
     }
     return PIC1D_OK;
 }
@@ -576,6 +582,30 @@ int enqueue_step(pic1d_state* st) {
         f.pair_sum = st->pair_sum; f.n_sum = st->n_sum; f.avg_count = st->avg_count; f.cell_line = st->cell_line;
         f.lines = st->dlines; f.n_total = nt; f.frozen = st->cfg.frozen_field; f.avg_start = st->cfg.avg_start_step;
         f.sc = st->sc;
+        if (st->cfg.annihilation) {
+            // pair annihilation at the density limit: plan and candidates here, the
+            // selection in k_field before Ampere
+            AnnihArgs& an = f.an;
+            an.cell = st->cell[b]; an.off = st->off[b]; an.u = st->u[b]; an.id = st->id[b];
+            an.seg_base = st->seg_base; an.seg_cap = st->seg_cap; an.alloc = st->alloc;
+            an.hist[0] = st->hist[0]; an.hist[1] = st->hist[1];
+            an.cell_line = st->cell_line; an.lines = st->dlines;
+            an.n_total = nt; an.n_lines = st->lay.n_lines;
+            an.ann_k = st->ann_k; an.ann_off = st->ann_off; an.ann_fill = st->ann_fill; an.ann_ctl = st->ann_ctl;
+            // candidate records in the other particle buffer set (written only by the sort)
+            an.cand_key = st->id[1 - b];
+            an.cand_slot = st->cell[1 - b];
+            an.cand_cap = st->lay.total_slots;
+            an.J = st->J; an.counters = st->counters;
+            an.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); an.key1 = (uint32_t)(st->cfg.seed >> 32);
+            an.sc = st->sc;
+            f.annihilation = 1;
+            const int pk = prof_begin(st, 5);
+            hipLaunchKernelGGL(k_annih_plan, dim3(std::min(st->aux_blocks, (nt + 255) / 256)), dim3(256), 0,
+                               st->stream, an);
+            hipLaunchKernelGGL(k_annih_gather, dim3(st->aux_blocks), dim3(256), 0, st->stream, an);
+            prof_end(st, pk);
+        }
         // Ampere; its block 0 also plans the next push and advances the step counter
         const int pk = prof_begin(st, 2);
         hipLaunchKernelGGL(k_field, dim3(std::min(st->aux_blocks, (nt + 255) / 256)), dim3(256), 0, st->stream, f,

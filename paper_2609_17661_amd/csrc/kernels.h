@@ -119,6 +119,37 @@ struct BookArgs {
     DevScalars* sc;
 };
 
+// Pair annihilation at the density limit (Sec. 3).  Per step, after the appends:
+// k_annih_plan sizes every cell's annihilation from its end-of-step counts,
+// k_annih_gather records the candidates (every e-/e+ of a cell over the limit),
+// and k_field selects and removes them before Ampere.  The candidate records
+// live in the particle buffer set the sort scatters into, idle between sorts.
+struct AnnihArgs {
+    int32_t* cell;              // the live particle buffer set
+    float* off;
+    float* u;
+    const uint64_t* id;
+    const int64_t* seg_base;
+    const int32_t* seg_cap;
+    const int32_t* alloc;       // slots in use per segment, appends included
+    int32_t* hist[2];           // per-cell counts, ping-pong by step parity
+    const int32_t* cell_line;
+    const LineDev* lines;
+    int32_t n_total;            // cells over all lines
+    int32_t n_lines;
+    int32_t* ann_k;             // per global cell: pairs to annihilate this step, 0 if none
+    int32_t* ann_off;           // per global cell: first candidate record (e- then e+)
+    int32_t* ann_fill;          // per global cell and species 0/1: candidates recorded
+    int32_t* ann_ctl;           // [0] records allocated, [1] cells over the limit (this step)
+    uint64_t* cand_key;         // candidate records: ranking key ...
+    int32_t* cand_slot;         // ... and slot within its species segment
+    int64_t cand_cap;           // records available
+    unsigned long long* J;
+    unsigned long long* counters;
+    uint32_t key0, key1;
+    DevScalars* sc;
+};
+
 struct FieldArgs {
     double* E;
     float* E32;
@@ -138,6 +169,9 @@ struct FieldArgs {
     int32_t frozen;
     int64_t avg_start;
     DevScalars* sc;
+    int32_t annihilation;       // 1: select and remove the planned annihilations first
+    int32_t pad;
+    AnnihArgs an;
 };
 
 struct SortArgs {
@@ -214,6 +248,8 @@ __global__ void k_rics_eval_mlp(PushArgs a, int line, int64_t n, const float* s_
 __global__ void k_append(ConvertArgs ca, AtmArgs aa, int conv_blocks);
 __global__ void k_plan(BookArgs b, int advance_step);
 __global__ void k_field(FieldArgs f, BookArgs b);
+__global__ void k_annih_plan(AnnihArgs a);
+__global__ void k_annih_gather(AnnihArgs a);
 __global__ void k_sort_zero(SortArgs s);
 __global__ void k_sort_count(SortArgs s);
 __global__ void k_sort_chunks(SortArgs s);

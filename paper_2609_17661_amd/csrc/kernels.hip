@@ -1045,6 +1045,192 @@ __global__ __launch_bounds__(256) void k_plan(BookArgs b, int advance_step) {
     if (advance_step && threadIdx.x == 0 && b.sc->err == 0) b.sc->step += 1;
 }
 
+// ---------------------------------------------------------------------------
+// Pair annihilation at the density limit (Sec. 3: pairs annihilate where the
+// total density approaches n_max, which keeps the skin depth resolved; the paper
+// gives no mechanics, so these are readings).  A cell whose end-of-step count N
+// of all particles exceeds n_max loses k = min(N-, N+, ceil((N - n_max)/2))
+// e-/e+ pairs (species 0 and 1): the k of each species with the smallest
+// (key, id), key the 64-bit Philox draw (step, id, STREAM_ANNIH), so the choice
+// does not depend on where the particles sit in memory.  Each pair annihilates
+// as if its positron first moved to its electron: the cell's face current gains
+// sum q(x-) - sum q(x+) in the deposit's fixed point (the same quantised
+// positions the push deposits from), and the neutral pair leaves no charge.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t annih_key(uint64_t step, uint64_t id, uint32_t k0, uint32_t k1) {
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)step, (uint32_t)id, (uint32_t)(id >> 32), STREAM_ANNIH),
+                                  k0, k1);
+    return ((uint64_t)w.y << 32) | (uint64_t)w.x;
+}
+
+// Block-wide (256 threads) exclusive scan of one int; writes the block total.
+__device__ __forceinline__ int block_excl_scan(int v, int& total) {
+    __shared__ int sWave[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) sWave[w] = inc;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = sWave[i];
+        before += i < w ? t : 0;
+        total += t;
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
+// Every cell's k from its end-of-step counts, and for the cells over the limit a
+// run of candidate records (their e- then their e+), one allocation per block.
+__global__ __launch_bounds__(256) void k_annih_plan(AnnihArgs a) {
+    if (a.sc->err != 0) return;
+    const uint64_t step = a.sc->step;
+    const int32_t* hist_out = a.hist[(step & 1) ^ 1];
+    __shared__ int s_base;
+    for (int g0 = blockIdx.x * 256; g0 < a.n_total; g0 += gridDim.x * 256) {
+        const int g = g0 + (int)threadIdx.x;
+        int k = 0, need = 0;
+        if (g < a.n_total) {
+            const int* h = hist_out + 4 * (size_t)g;
+            const int h0 = h[0], h1 = h[1];
+            const int N = h0 + h1 + h[2] + h[3];
+            const double nmax = (double)a.lines[a.cell_line[g]].nmax;
+            if ((double)N > nmax) k = (int)fmin(fmin((double)h0, (double)h1), ceil(((double)N - nmax) * 0.5));
+            need = k > 0 ? h0 + h1 : 0;
+        }
+        int total = 0;
+        const int excl = block_excl_scan(need, total);
+        if (total > 0 && threadIdx.x == 0) {
+            s_base = atomicAdd(&a.ann_ctl[0], total);
+            atomicOr(&a.ann_ctl[1], 1);
+        }
+        __syncthreads();
+        if (k > 0) {
+            const int64_t off = (int64_t)s_base + excl;
+            if (off + need > a.cand_cap || off + need > (int64_t)INT32_MAX) {
+                set_error(&a.sc->err, -3);
+                k = 0;
+            } else {
+                a.ann_off[g] = (int)off;
+                a.ann_fill[2 * (size_t)g] = 0;
+                a.ann_fill[2 * (size_t)g + 1] = 0;
+            }
+        }
+        if (g < a.n_total) a.ann_k[g] = k;
+        __syncthreads();
+    }
+}
+
+// The candidates: every live e- and e+ (appends included) in a cell over the
+// limit records its key and slot.  Exits at once when no cell is over it.
+__global__ __launch_bounds__(256) void k_annih_gather(AnnihArgs a) {
+    if (a.sc->err != 0 || a.ann_ctl[1] == 0) return;
+    const uint64_t step = a.sc->step;
+    const int32_t* hist_out = a.hist[(step & 1) ^ 1];
+    const int stride = gridDim.x * 256;
+    for (int l = 0; l < a.n_lines; ++l) {
+        const int cb = a.lines[l].cell_base;
+        for (int s = 0; s < 2; ++s) {
+            const int seg = 4 * l + s;
+            const int n = min(a.alloc[seg], a.seg_cap[seg]);
+            const int64_t base = a.seg_base[seg];
+            for (int i = blockIdx.x * 256 + (int)threadIdx.x; i < n; i += stride) {
+                const int c = a.cell[base + i];
+                if (c == DEAD_CELL) continue;
+                const int g = cb + c;
+                if (a.ann_k[g] == 0) continue;
+                const int r = atomicAdd(&a.ann_fill[2 * (size_t)g + s], 1);
+                const int* h = hist_out + 4 * (size_t)g;
+                if (r >= h[s]) {              // counts and particles disagree: cannot happen
+                    set_error(&a.sc->err, -4);
+                    continue;
+                }
+                const int64_t rec = (int64_t)a.ann_off[g] + (s ? h[0] : 0) + r;
+                a.cand_key[rec] = annih_key(step, a.id[base + i], a.key0, a.key1);
+                a.cand_slot[rec] = i;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wavefront removes cell g's k annihilating pairs (every lane calls it with
+// the same g and k): per species a most-significant-bit-first radix select finds
+// the k-th smallest key, keys below it are taken and keys equal to it (in
+// practice only itself) by rank of id.  Returns (to every lane) the annihilation
+// current in the deposit's units (2^-28 cell); the caller adds it to J[g] and
+// takes k off the cell's e-/e+ counts.
+__device__ long long annihilate_cell(const AnnihArgs& a, const int32_t* hist_out, int g, int k) {
+    const int lane = threadIdx.x & 63;
+    const int line = a.cell_line[g];
+    const int* h = hist_out + 4 * (size_t)g;
+    const int h0 = h[0], h1 = h[1];
+    // every e- and e+ of the cell must have been recorded (records beyond those
+    // written hold stale data of the other buffer set and are never read)
+    if (a.ann_fill[2 * (size_t)g] != h0 || a.ann_fill[2 * (size_t)g + 1] != h1) {
+        if (lane == 0) set_error(&a.sc->err, -4);
+        return 0;
+    }
+    long long dq = 0;
+    for (int s = 0; s < 2; ++s) {
+        const int m = s ? h1 : h0;
+        const int64_t rec0 = (int64_t)a.ann_off[g] + (s ? h0 : 0);
+        const int64_t base = a.seg_base[4 * line + s];
+        uint64_t kth = 0;
+        int want = k;                 // rank sought among the keys that match kth so far
+        for (int b = 63; b >= 0; --b) {
+            const uint64_t above = b == 63 ? 0ull : (~0ull << (b + 1));
+            int c = 0;
+            for (int r = lane; r < m; r += 64) {
+                const uint64_t key = a.cand_key[rec0 + r];
+                c += ((key & above) == kth && ((key >> b) & 1ull) == 0ull) ? 1 : 0;
+            }
+            c = wave_sum_i(c);
+            if (want > c) {
+                want -= c;
+                kth |= 1ull << b;
+            }
+        }
+        // kth is the k-th smallest key; `want` of the keys equal to it are taken
+        for (int r = lane; r < m; r += 64) {
+            const uint64_t key = a.cand_key[rec0 + r];
+            const int slot = a.cand_slot[rec0 + r];
+            bool take = key < kth;
+            if (key == kth) {
+                const uint64_t id = a.id[base + slot];
+                int below = 0;
+                for (int r2 = 0; r2 < m; ++r2)
+                    below += (a.cand_key[rec0 + r2] == kth && a.id[base + a.cand_slot[rec0 + r2]] < id) ? 1 : 0;
+                take = below < want;
+            }
+            if (take) {
+                const int64_t kidx = base + slot;
+                const long long q = (long long)(int)(a.off[kidx] * POS_SCALE);
+                dq += s == 0 ? q : -q;
+                a.cell[kidx] = DEAD_CELL;
+                a.off[kidx] = 0.5f;
+                a.u[kidx] = 0.0f;
+            }
+        }
+    }
+    if (lane == 0)
+        atomicAdd(&a.counters[((size_t)line * CNT_REPL + (blockIdx.x & (CNT_REPL - 1))) * NCOUNT + 11],
+                  (unsigned long long)k);
+    return wave_sum_ll(dq);
+}
+
 // Ampere's law with the static twist current (Sec. 3): E -= 4 pi (j - j_twist),
 // plus time averages and the reset of the step's accumulators.  Block 0 also does
 // the step's bookkeeping (live counts, the next push's tile plan) and advances the
@@ -1059,12 +1245,39 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
     const int n = f.n_total;
     const int hin = (int)(step & 1);
     int* hist_in = f.hist[hin];
-    const int* hist_out = f.hist[hin ^ 1];
+    int* hist_out = f.hist[hin ^ 1];
     const bool averaging = f.avg_start >= 0 && step >= (uint64_t)f.avg_start;
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && f.annihilation) {
+        // the plan of the next step allocates from zero (no other block reads these)
+        f.an.ann_ctl[0] = 0;
+        f.an.ann_ctl[1] = 0;
+    }
+    for (int g0 = blockIdx.x * blockDim.x; g0 < n; g0 += gridDim.x * blockDim.x) {
+        const int g = g0 + (int)threadIdx.x;
+        long long dJ = 0;        // this lane's cell: annihilation current and pairs removed
+        int k_own = 0;
+        if (f.annihilation) {
+            // this wavefront's cells over the limit, one at a time, before their Ampere
+            const int k = g < n ? f.an.ann_k[g] : 0;
+            unsigned long long m = __ballot(k > 0);
+            while (m != 0ull) {
+                const int lead = __ffsll((long long)m) - 1;
+                m &= m - 1ull;
+                const long long d = annihilate_cell(f.an, hist_out, __shfl(g, lead, 64), __shfl(k, lead, 64));
+                if ((int)(threadIdx.x & 63) == lead) {
+                    dJ = d;
+                    k_own = k;
+                }
+            }
+            if (k_own > 0) {
+                hist_out[4 * (size_t)g] -= k_own;
+                hist_out[4 * (size_t)g + 1] -= k_own;
+            }
+        }
+        if (g >= n) continue;
         const int line = f.cell_line[g];
         const LineDev& L = f.lines[line];
-        const long long J = (long long)f.J[g];
+        const long long J = (long long)f.J[g] + dJ * (1ll << POS_TO_FIX);
         const double j = (double)J * FIX_INV * L.Q;
         f.J[g] = 0ull;
         f.j_last[g] = j;

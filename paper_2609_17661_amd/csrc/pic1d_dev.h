@@ -34,7 +34,7 @@ constexpr float Y_CUT = 80.0f;                    // Planck factors vanish beyon
 
 // Philox stream tags (fourth counter word of each draw).
 constexpr uint32_t STREAM_INIT = 1, STREAM_RICS = 2, STREAM_CHILD = 3,
-                   STREAM_ATM_A = 4, STREAM_ATM_B = 5, STREAM_ATM_ID = 6;
+                   STREAM_ATM_A = 4, STREAM_ATM_B = 5, STREAM_ATM_ID = 6, STREAM_ANNIH = 7;
 constexpr uint64_t HASHED_ID_BIT = 1ull << 63;
 
 // Per-line constants, precomputed on the host in FP64.

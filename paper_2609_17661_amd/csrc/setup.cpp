@@ -81,6 +81,7 @@ const char* validate_config(const pic1d_config* c) {
     if (!(c->cfl > 0.0 && c->cfl <= 0.5)) return "cfl must be in (0, 0.5]";
     if (!(c->d0_cells > 0.0) || !(c->ppc0 > 0.0)) return "d0_cells and ppc0 must be positive";
     if (!(c->kT_keV > 0.0) || !(c->b_pole > 0.0)) return "kT_keV and b_pole must be positive";
+    if (c->annihilation != 0 && c->annihilation != 1) return "annihilation must be 0 or 1";
     if (!(c->mass_ratio >= 1.0)) return "mass_ratio must be >= 1";
     if (!(c->eta_min > 0.0)) return "eta_min must be positive";
     if (c->rics_backend < 0 || c->rics_backend > 3) return "unknown rics_backend";

@@ -39,6 +39,7 @@ class CConfig(ctypes.Structure):
                 ("rics_backend", ctypes.c_int32), ("table_nlg", ctypes.c_int32), ("table_ns", ctypes.c_int32),
                 ("pairs", ctypes.c_int32), ("conversion", ctypes.c_int32), ("atmosphere", ctypes.c_int32),
                 ("gravity", ctypes.c_int32), ("frozen_field", ctypes.c_int32),
+                ("annihilation", ctypes.c_int32), ("pad1", ctypes.c_int32),
                 ("nmax_over_n0", ctypes.c_double), ("atm_a0", ctypes.c_double), ("atm_h_cells", ctypes.c_double),
                 ("atm_T", ctypes.c_double), ("atm_cut", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("sort_interval", ctypes.c_int32), ("avg_start_step", ctypes.c_int32),
@@ -56,14 +57,14 @@ class CMoments(ctypes.Structure):
 
 
 COUNTER_NAMES = ("events", "pairs_created", "photons_escaped", "absorbed", "psc_clipped", "limited",
-                 "newton", "atm_injected", "pushed", "draws", "mlp_evals")
+                 "newton", "atm_injected", "pushed", "draws", "mlp_evals", "annihilated")
 
 
 class CProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
 
 
-KERNELS = ("push", "append", "field", "plan", "sort")
+KERNELS = ("push", "append", "field", "plan", "sort", "annihilate")
 
 
 class CTuneOut(ctypes.Structure):
@@ -169,6 +170,7 @@ def make_cconfig(cfg):
     c.atmosphere = int(bool(cfg["atmosphere"]))
     c.gravity = int(bool(cfg["gravity"]))
     c.frozen_field = int(bool(cfg["frozen_field"]))
+    c.annihilation = int(bool(cfg["annihilation"]))
     c.seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
     c.sort_interval = int(cfg["sort_interval"])
     c.avg_start_step = int(cfg["avg_start_step"])

@@ -74,6 +74,12 @@ CASES = {
     # float64 form
     "table-rows-per-cell": workloads.small(n_cells=400, ppc=6, rics="table", table_nlg=96, table_ns=37,
                                            pairs=True, conversion="curvature"),
+    # n_max = 1.5 n0 against 2 n0 at the start: every cell annihilates in the first
+    # step, fluctuations over the limit afterwards
+    "annihilation-exact-hot": workloads.small(n_cells=64, ppc=16, rics="exact", pairs=True, nmax_over_n0=1.5),
+    "annihilation-table-atmosphere": workloads.small(n_cells=200, ppc=12, rics="table", table_nlg=64,
+                                                     table_ns=96, pairs=True, conversion="curvature",
+                                                     atmosphere=True, nmax_over_n0=1.5),
 }
 
 
@@ -170,6 +176,40 @@ def test_result_independent_of_sorting_and_bitwise_reproducible():
             np.testing.assert_array_equal(a[s][k], c[s][k])
     np.testing.assert_array_equal(Ea, Eb)
     np.testing.assert_array_equal(Ea, Ec)
+
+
+def test_annihilation_holds_cells_at_the_limit_independently_of_sorting():
+    """With n_max below the initial density: pairs annihilate every step, every cell
+    that keeps both e- and e+ ends each step at or below n_max, Gauss's law holds,
+    and the result does not depend on the particle order (sorted every step, every
+    3 steps, never)."""
+    # (no atmosphere: on a line this short its layer fills every cell far beyond n_max)
+    base = workloads.small(n_cells=96, ppc=20, rics="exact", pairs=True, nmax_over_n0=1.2)
+    n_max = 1.2 * 20
+    finals = []
+    for interval in (0, 1, 3):
+        sim = _sim(dict(base, sort_interval=interval))
+        for _ in range(3):
+            sim.step(4)
+            P = [sim.get_particles(0, s) for s in range(4)]
+            counts = sum(np.bincount(Q["cell"], minlength=96) for Q in P)
+            both = (np.bincount(P[0]["cell"], minlength=96) > 0) & (np.bincount(P[1]["cell"], minlength=96) > 0)
+            assert counts[both].max() <= n_max
+            m = sim.moments(0)
+            assert m["gauss_residual"] <= 1e-6
+        assert m["counters"]["annihilated"] > 20 * 96 * 0.2
+        out = {}
+        for s in range(4):
+            Q = sim.get_particles(0, s)
+            o = np.argsort(Q["id"])
+            out[s] = {k: v[o] for k, v in Q.items()}
+        finals.append((out, sim.get_field(0)))
+        _print("sort interval", interval, "annihilated", m["counters"]["annihilated"])
+    for out, E in finals[1:]:
+        for s in range(4):
+            for k in ("id", "cell", "off", "u"):
+                np.testing.assert_array_equal(out[s][k], finals[0][0][s][k])
+        np.testing.assert_array_equal(E, finals[0][1])
 
 
 def test_sort_orders_particles_by_position():
