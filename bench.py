@@ -319,23 +319,26 @@ def cascade_run(chunks, chunk_steps, profile_steps):
     seed_pairs = sum(l["ppc_init"] * l["n_cells"] for l in cfg["lines"])
     n_start = live(sim)
     sim.set_graph(100)          # the seed evolves fastest at first: no launch trials before it
-    rows, pairs, wall = [], 0, 0.0
+    rows, pairs, annihilated, wall = [], 0, 0, 0.0
     for c in range(chunks):
         r = timed_run(sim, chunk_steps, 0, profile=False)
         pairs += r["counters"]["pairs_created"]
+        annihilated += r["counters"]["annihilated"]
         wall += r["ms"] * 1e-3
         rows.append({"steps_done": (c + 1) * chunk_steps, "ms_per_step": r["ms_per_step"],
-                     "particle_steps_per_s": r["value"], "particles": live(sim), "pairs_created": pairs})
+                     "particle_steps_per_s": r["value"], "particles": live(sim), "pairs_created": pairs,
+                     "pairs_annihilated": annihilated})
         print(f"# cascade chunk {c}: {rows[-1]}", file=sys.stderr, flush=True)
     rp = timed_run(sim, profile_steps, 0, profile=True)
     bytes_per_launch = hbm_bytes_per_launch(rp)
     gauss = max(sim.moments(li)["gauss_residual"] for li in range(sim.n_lines))
     out = {"workload": f"cfg5: {sim.n_lines} lines, R_max log-uniform in [10, 100], 32768 cells each, hot pair "
                        f"seed {cfg['lines'][0]['ppc_init']} e-/e+ per cell (gamma to 1e4), n_max = 6 n0 (n0 = 32), atmosphere with ions at "
-                       f"m_i/m_e = 100, pairs (curvature), TABLE RICS, 100-step graphs",
+                       f"m_i/m_e = 100, pairs (curvature), pair annihilation over n_max, TABLE RICS, 100-step graphs",
            "init_seconds": t_init, "wall_seconds": wall, "steps": chunks * chunk_steps,
            "particles_start": n_start, "particles_end": rows[-1]["particles"],
-           "pair_multiplicity": pairs / seed_pairs, "chunks": rows,
+           "pair_multiplicity": pairs / seed_pairs, "pairs_annihilated": annihilated, "chunks": rows,
+           "kernels_ms_at_end": rp["kernels_ms"],
            "k_push_ms_at_end": rp["push_avg_s"] * 1e3,
            "hbm_GBps_at_end": bytes_per_launch / rp["push_avg_s"] / 1e9,
            "roofline_frac_at_end": bytes_per_launch / rp["push_avg_s"] / HBM_PEAK,

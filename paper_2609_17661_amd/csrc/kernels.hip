@@ -1128,42 +1128,71 @@ __global__ __launch_bounds__(256) void k_annih_plan(AnnihArgs a) {
     }
 }
 
-// The candidates: every live e- and e+ (appends included) in a cell over the
-// limit records its key and slot.  Exits at once when no cell is over it.
-__global__ __launch_bounds__(256) void k_annih_gather(AnnihArgs a) {
-    if (a.sc->err != 0 || a.ann_ctl[1] == 0) return;
-    const uint64_t step = a.sc->step;
-    const int32_t* hist_out = a.hist[(step & 1) ^ 1];
-    const int stride = gridDim.x * 256;
-    for (int l = 0; l < a.n_lines; ++l) {
-        const int cb = a.lines[l].cell_base;
-        for (int s = 0; s < 2; ++s) {
-            const int seg = 4 * l + s;
-            const int n = min(a.alloc[seg], a.seg_cap[seg]);
-            const int64_t base = a.seg_base[seg];
-            for (int i = blockIdx.x * 256 + (int)threadIdx.x; i < n; i += stride) {
-                const int c = a.cell[base + i];
-                if (c == DEAD_CELL) continue;
-                const int g = cb + c;
-                if (a.ann_k[g] == 0) continue;
-                const int r = atomicAdd(&a.ann_fill[2 * (size_t)g + s], 1);
-                const int* h = hist_out + 4 * (size_t)g;
-                if (r >= h[s]) {              // counts and particles disagree: cannot happen
-                    set_error(&a.sc->err, -4);
-                    continue;
-                }
-                const int64_t rec = (int64_t)a.ann_off[g] + (s ? h[0] : 0) + r;
-                a.cand_key[rec] = annih_key(step, a.id[base + i], a.key0, a.key1);
-                a.cand_slot[rec] = i;
-            }
-        }
-    }
-}
-
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// Candidates per lane held in registers by the fast selection (k <= ANNIH_FAST_K
+// of at most 64 * ANNIH_KPL candidates per species); larger cells take the
+// radix select over the records in memory.
+constexpr int ANNIH_KPL = 8;
+constexpr int ANNIH_FAST_K = 16;
+
+// The `k` smallest (key, id) of one species' m candidates, extracted one at a
+// time by wave-wide minima over the keys held in registers; ids are read only
+// to break an exact tie of keys.  Bit j of the result: the lane's j-th
+// candidate (record lane + 64 j) is taken.
+__device__ uint32_t annih_fast_select(const AnnihArgs& a, int64_t rec0, int64_t base, int m, int k) {
+    const int lane = threadIdx.x & 63;
+    uint64_t key[ANNIH_KPL];
+#pragma unroll
+    for (int j = 0; j < ANNIH_KPL; ++j) {
+        const int r = lane + 64 * j;
+        key[j] = r < m ? a.cand_key[rec0 + r] : ~0ull;
+    }
+    uint32_t taken = 0;
+    for (int round = 0; round < k; ++round) {
+        uint64_t mine = ~0ull;
+#pragma unroll
+        for (int j = 0; j < ANNIH_KPL; ++j)
+            if (!((taken >> j) & 1u) && lane + 64 * j < m && key[j] < mine) mine = key[j];
+        const uint64_t kmin = wave_min_u64(mine);
+        int ties = 0;
+#pragma unroll
+        for (int j = 0; j < ANNIH_KPL; ++j)
+            ties += (!((taken >> j) & 1u) && lane + 64 * j < m && key[j] == kmin) ? 1 : 0;
+        const int all_ties = wave_sum_i(ties);
+        if (all_ties == 1) {
+#pragma unroll
+            for (int j = 0; j < ANNIH_KPL; ++j)
+                if (!((taken >> j) & 1u) && lane + 64 * j < m && key[j] == kmin) taken |= 1u << j;
+        } else {
+            // equal keys: the smallest id among them
+            uint64_t idmin = ~0ull;
+            int jmin = -1;
+#pragma unroll
+            for (int j = 0; j < ANNIH_KPL; ++j) {
+                if (!((taken >> j) & 1u) && lane + 64 * j < m && key[j] == kmin) {
+                    const uint64_t id = a.id[base + a.cand_slot[rec0 + lane + 64 * j]];
+                    if (id < idmin) { idmin = id; jmin = j; }
+                }
+            }
+            const uint64_t wid = wave_min_u64(idmin);
+            if (jmin >= 0 && idmin == wid) taken |= 1u << jmin;
+        }
+    }
+    return taken;
 }
 
 // One wavefront removes cell g's k annihilating pairs (every lane calls it with
@@ -1188,6 +1217,21 @@ __device__ long long annihilate_cell(const AnnihArgs& a, const int32_t* hist_out
         const int m = s ? h1 : h0;
         const int64_t rec0 = (int64_t)a.ann_off[g] + (s ? h0 : 0);
         const int64_t base = a.seg_base[4 * line + s];
+        if (k <= ANNIH_FAST_K && m <= 64 * ANNIH_KPL) {
+            const uint32_t taken = annih_fast_select(a, rec0, base, m, k);
+#pragma unroll
+            for (int j = 0; j < ANNIH_KPL; ++j) {
+                if ((taken >> j) & 1u) {
+                    const int64_t kidx = base + a.cand_slot[rec0 + lane + 64 * j];
+                    const long long q = (long long)(int)(a.off[kidx] * POS_SCALE);
+                    dq += s == 0 ? q : -q;
+                    a.cell[kidx] = DEAD_CELL;
+                    a.off[kidx] = 0.5f;
+                    a.u[kidx] = 0.0f;
+                }
+            }
+            continue;
+        }
         uint64_t kth = 0;
         int want = k;                 // rank sought among the keys that match kth so far
         for (int b = 63; b >= 0; --b) {
@@ -1340,6 +1384,47 @@ __device__ __forceinline__ unsigned long long match_key(int key, bool active, in
         act &= ~m;
     }
     return mine;
+}
+
+// The candidates: every live e- and e+ (appends included) in a cell over the
+// limit records its key and slot.  Exits at once when no cell is over it.  Lanes
+// of a wavefront in the same cell reserve their records with one atomic.
+__global__ __launch_bounds__(256) void k_annih_gather(AnnihArgs a) {
+    if (a.sc->err != 0 || a.ann_ctl[1] == 0) return;
+    const uint64_t step = a.sc->step;
+    const int32_t* hist_out = a.hist[(step & 1) ^ 1];
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int stride = gridDim.x * 256;
+    for (int l = 0; l < a.n_lines; ++l) {
+        const int cb = a.lines[l].cell_base;
+        for (int s = 0; s < 2; ++s) {
+            const int seg = 4 * l + s;
+            const int n = min(a.alloc[seg], a.seg_cap[seg]);
+            const int64_t base = a.seg_base[seg];
+            for (int i0 = blockIdx.x * 256; i0 < n; i0 += stride) {      // block-uniform trip count
+                const int i = i0 + (int)threadIdx.x;
+                const int c = i < n ? a.cell[base + i] : DEAD_CELL;
+                const int g = c != DEAD_CELL ? cb + c : 0;
+                const bool cand = c != DEAD_CELL && a.ann_k[g] != 0;
+                if (__ballot(cand) == 0ull) continue;                     // wave-uniform
+                int leader;
+                const unsigned long long mm = match_key(g, cand, leader);
+                int r0 = 0;
+                if (cand && lane == leader) r0 = atomicAdd(&a.ann_fill[2 * (size_t)g + s], __popcll(mm));
+                const int r = __shfl(r0, leader, 64) + __popcll(mm & below);
+                if (!cand) continue;
+                const int* h = hist_out + 4 * (size_t)g;
+                if (r >= h[s]) {              // counts and particles disagree: cannot happen
+                    set_error(&a.sc->err, -4);
+                    continue;
+                }
+                const int64_t rec = (int64_t)a.ann_off[g] + (s ? h[0] : 0) + r;
+                a.cand_key[rec] = annih_key(step, a.id[base + i], a.key0, a.key1);
+                a.cand_slot[rec] = i;
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_sort_zero(SortArgs s) {
