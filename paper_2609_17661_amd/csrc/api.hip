@@ -608,8 +608,10 @@ int enqueue_step(pic1d_state* st) {
         }
         // Ampere; its block 0 also plans the next push and advances the step counter
         const int pk = prof_begin(st, 2);
-        hipLaunchKernelGGL(k_field, dim3(std::min(st->aux_blocks, (nt + 255) / 256)), dim3(256), 0, st->stream, f,
-                           book_args(st));
+        // 64 cells per wavefront, 16 with annihilation (k_field's cells per wavefront)
+        const int field_cells = f.annihilation ? 64 : 256;
+        hipLaunchKernelGGL(k_field, dim3(std::min(4 * st->aux_blocks, (nt + field_cells - 1) / field_cells)), dim3(256),
+                           0, st->stream, f, book_args(st));
         prof_end(st, pk);
         st->host_step += 1;
         if (st->cfg.sort_interval > 0 && st->host_step % st->cfg.sort_interval == 0) {

@@ -1143,17 +1143,19 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
     return v;
 }
 
-// Candidates per lane held in registers by the fast selection (k <= ANNIH_FAST_K
-// of at most 64 * ANNIH_KPL candidates per species); larger cells take the
-// radix select over the records in memory.
+// Candidates per lane held in registers by the register selection (at most
+// 64 * ANNIH_KPL candidates of a species); larger cells take the radix select
+// over the records in memory.
 constexpr int ANNIH_KPL = 8;
-constexpr int ANNIH_FAST_K = 16;
+constexpr int ANNIH_EXTRACT_K = 8;
 
-// The `k` smallest (key, id) of one species' m candidates, extracted one at a
-// time by wave-wide minima over the keys held in registers; ids are read only
-// to break an exact tie of keys.  Bit j of the result: the lane's j-th
-// candidate (record lane + 64 j) is taken.
-__device__ uint32_t annih_fast_select(const AnnihArgs& a, int64_t rec0, int64_t base, int m, int k) {
+// The `k` smallest (key, id) of one species' m candidates, with the keys in
+// registers: for k <= ANNIH_EXTRACT_K extracted one at a time by wave-wide
+// minima, else an 8-bit radix select on a per-wavefront LDS histogram `hist`
+// (256 ints) followed by the keys below the k-th.  Ids are read only where keys
+// tie exactly.  Bit j of the result: the lane's j-th candidate (record
+// lane + 64 j) is taken.
+__device__ uint32_t annih_select_regs(const AnnihArgs& a, int64_t rec0, int64_t base, int m, int k, int* hist) {
     const int lane = threadIdx.x & 63;
     uint64_t key[ANNIH_KPL];
 #pragma unroll
@@ -1161,29 +1163,16 @@ __device__ uint32_t annih_fast_select(const AnnihArgs& a, int64_t rec0, int64_t 
         const int r = lane + 64 * j;
         key[j] = r < m ? a.cand_key[rec0 + r] : ~0ull;
     }
+    auto valid = [&](int j) { return lane + 64 * j < m; };
     uint32_t taken = 0;
-    for (int round = 0; round < k; ++round) {
-        uint64_t mine = ~0ull;
-#pragma unroll
-        for (int j = 0; j < ANNIH_KPL; ++j)
-            if (!((taken >> j) & 1u) && lane + 64 * j < m && key[j] < mine) mine = key[j];
-        const uint64_t kmin = wave_min_u64(mine);
-        int ties = 0;
-#pragma unroll
-        for (int j = 0; j < ANNIH_KPL; ++j)
-            ties += (!((taken >> j) & 1u) && lane + 64 * j < m && key[j] == kmin) ? 1 : 0;
-        const int all_ties = wave_sum_i(ties);
-        if (all_ties == 1) {
-#pragma unroll
-            for (int j = 0; j < ANNIH_KPL; ++j)
-                if (!((taken >> j) & 1u) && lane + 64 * j < m && key[j] == kmin) taken |= 1u << j;
-        } else {
-            // equal keys: the smallest id among them
+    // take `n` more of the untaken candidates whose key is kmin, smallest id first
+    auto take_ties = [&](uint64_t kmin, int n) {
+        for (int t = 0; t < n; ++t) {
             uint64_t idmin = ~0ull;
             int jmin = -1;
 #pragma unroll
             for (int j = 0; j < ANNIH_KPL; ++j) {
-                if (!((taken >> j) & 1u) && lane + 64 * j < m && key[j] == kmin) {
+                if (!((taken >> j) & 1u) && valid(j) && key[j] == kmin) {
                     const uint64_t id = a.id[base + a.cand_slot[rec0 + lane + 64 * j]];
                     if (id < idmin) { idmin = id; jmin = j; }
                 }
@@ -1191,6 +1180,77 @@ __device__ uint32_t annih_fast_select(const AnnihArgs& a, int64_t rec0, int64_t 
             const uint64_t wid = wave_min_u64(idmin);
             if (jmin >= 0 && idmin == wid) taken |= 1u << jmin;
         }
+    };
+    if (k <= ANNIH_EXTRACT_K) {
+        for (int round = 0; round < k; ++round) {
+            uint64_t mine = ~0ull;
+#pragma unroll
+            for (int j = 0; j < ANNIH_KPL; ++j)
+                if (!((taken >> j) & 1u) && valid(j) && key[j] < mine) mine = key[j];
+            const uint64_t kmin = wave_min_u64(mine);
+            int ties = 0;
+#pragma unroll
+            for (int j = 0; j < ANNIH_KPL; ++j) ties += (!((taken >> j) & 1u) && valid(j) && key[j] == kmin) ? 1 : 0;
+            if (wave_sum_i(ties) == 1) {
+#pragma unroll
+                for (int j = 0; j < ANNIH_KPL; ++j)
+                    if (valid(j) && key[j] == kmin) taken |= 1u << j;
+            } else {
+                take_ties(kmin, 1);
+            }
+        }
+        return taken;
+    }
+    // radix select, most significant byte first: kth ends as the k-th smallest key
+    uint64_t kth = 0;
+    int want = k;
+    for (int p = 7; p >= 0; --p) {
+        const int sh = 8 * p;
+        for (int i = lane; i < 256; i += 64) hist[i] = 0;
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < ANNIH_KPL; ++j) {
+            const bool match = valid(j) && (p == 7 || (key[j] >> (sh + 8)) == (kth >> (sh + 8)));
+            if (match) atomicAdd(&hist[(int)((key[j] >> sh) & 255ull)], 1);
+        }
+        wave_sync();
+        const int c0 = hist[4 * lane], c1 = hist[4 * lane + 1], c2 = hist[4 * lane + 2], c3 = hist[4 * lane + 3];
+        const int t = c0 + c1 + c2 + c3;
+        int inc = t;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        const int excl = inc - t;
+        const unsigned long long hb = __ballot(excl < want && want <= inc);
+        const int L = __ffsll((long long)hb) - 1;
+        int d = 0, below = excl;
+        if (lane == L) {
+            const int w = want - excl;
+            if (w <= c0) { d = 0; }
+            else if (w <= c0 + c1) { d = 1; below += c0; }
+            else if (w <= c0 + c1 + c2) { d = 2; below += c0 + c1; }
+            else { d = 3; below += c0 + c1 + c2; }
+        }
+        d = __shfl(d, L, 64);
+        below = __shfl(below, L, 64);
+        kth |= (uint64_t)(4 * L + d) << sh;
+        want -= below;
+        wave_sync();
+    }
+    int eq = 0;
+#pragma unroll
+    for (int j = 0; j < ANNIH_KPL; ++j) {
+        if (valid(j) && key[j] < kth) taken |= 1u << j;
+        eq += (valid(j) && key[j] == kth) ? 1 : 0;
+    }
+    if (wave_sum_i(eq) == want) {
+#pragma unroll
+        for (int j = 0; j < ANNIH_KPL; ++j)
+            if (valid(j) && key[j] == kth) taken |= 1u << j;
+    } else {
+        take_ties(kth, want);
     }
     return taken;
 }
@@ -1201,7 +1261,7 @@ __device__ uint32_t annih_fast_select(const AnnihArgs& a, int64_t rec0, int64_t 
 // practice only itself) by rank of id.  Returns (to every lane) the annihilation
 // current in the deposit's units (2^-28 cell); the caller adds it to J[g] and
 // takes k off the cell's e-/e+ counts.
-__device__ long long annihilate_cell(const AnnihArgs& a, const int32_t* hist_out, int g, int k) {
+__device__ long long annihilate_cell(const AnnihArgs& a, const int32_t* hist_out, int g, int k, int* hist) {
     const int lane = threadIdx.x & 63;
     const int line = a.cell_line[g];
     const int* h = hist_out + 4 * (size_t)g;
@@ -1217,8 +1277,8 @@ __device__ long long annihilate_cell(const AnnihArgs& a, const int32_t* hist_out
         const int m = s ? h1 : h0;
         const int64_t rec0 = (int64_t)a.ann_off[g] + (s ? h0 : 0);
         const int64_t base = a.seg_base[4 * line + s];
-        if (k <= ANNIH_FAST_K && m <= 64 * ANNIH_KPL) {
-            const uint32_t taken = annih_fast_select(a, rec0, base, m, k);
+        if (m <= 64 * ANNIH_KPL) {
+            const uint32_t taken = annih_select_regs(a, rec0, base, m, k, hist);
 #pragma unroll
             for (int j = 0; j < ANNIH_KPL; ++j) {
                 if ((taken >> j) & 1u) {
@@ -1296,19 +1356,28 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
         f.an.ann_ctl[0] = 0;
         f.an.ann_ctl[1] = 0;
     }
-    for (int g0 = blockIdx.x * blockDim.x; g0 < n; g0 += gridDim.x * blockDim.x) {
-        const int g = g0 + (int)threadIdx.x;
+    // Each wavefront takes FIELD_CPW consecutive cells per iteration (all 64 lanes
+    // when annihilation is off; 16 when on, so that more wavefronts share the
+    // selections of the cells over the limit).
+    __shared__ int sHist[4][256];            // per wavefront: the radix histogram of the selection
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int cpw = f.annihilation ? 16 : 64;
+    const int wpb = blockDim.x >> 6;
+    for (int gw = (blockIdx.x * wpb + wid) * cpw; gw < n; gw += gridDim.x * wpb * cpw) {
+        const int g = gw + lane;
+        const bool own = lane < cpw && g < n;
         long long dJ = 0;        // this lane's cell: annihilation current and pairs removed
         int k_own = 0;
         if (f.annihilation) {
             // this wavefront's cells over the limit, one at a time, before their Ampere
-            const int k = g < n ? f.an.ann_k[g] : 0;
+            const int k = own ? f.an.ann_k[g] : 0;
             unsigned long long m = __ballot(k > 0);
             while (m != 0ull) {
                 const int lead = __ffsll((long long)m) - 1;
                 m &= m - 1ull;
-                const long long d = annihilate_cell(f.an, hist_out, __shfl(g, lead, 64), __shfl(k, lead, 64));
-                if ((int)(threadIdx.x & 63) == lead) {
+                const long long d = annihilate_cell(f.an, hist_out, __shfl(g, lead, 64), __shfl(k, lead, 64),
+                                                    sHist[wid]);
+                if (lane == lead) {
                     dJ = d;
                     k_own = k;
                 }
@@ -1318,7 +1387,7 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
                 hist_out[4 * (size_t)g + 1] -= k_own;
             }
         }
-        if (g >= n) continue;
+        if (!own) continue;
         const int line = f.cell_line[g];
         const LineDev& L = f.lines[line];
         const long long J = (long long)f.J[g] + dJ * (1ll << POS_TO_FIX);

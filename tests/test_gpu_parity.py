@@ -77,9 +77,12 @@ CASES = {
     # n_max = 1.5 n0 against 2 n0 at the start: every cell annihilates in the first
     # step, fluctuations over the limit afterwards
     "annihilation-exact-hot": workloads.small(n_cells=64, ppc=16, rics="exact", pairs=True, nmax_over_n0=1.5),
-    # k = 30 pairs per cell in the first step: the selection by radix over the
-    # records in memory (small k takes the register path)
+    # k = 30 pairs per cell in the first step: the radix selection in registers
+    # (k <= 8 takes the extraction by wave minima)
     "annihilation-large-excess": workloads.small(n_cells=48, ppc=40, rics="exact", nmax_over_n0=0.5),
+    # 600 e- and e+ per cell (more than the register selection holds), k = 450:
+    # the radix selection over the records in memory
+    "annihilation-dense-cells": workloads.small(n_cells=16, ppc=600, rics="exact", nmax_over_n0=0.5),
     "annihilation-table-atmosphere": workloads.small(n_cells=200, ppc=12, rics="table", table_nlg=64,
                                                      table_ns=96, pairs=True, conversion="curvature",
                                                      atmosphere=True, nmax_over_n0=1.5),
