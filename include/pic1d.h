@@ -264,7 +264,9 @@ typedef struct {
 /* Autotuner of the launch shape: times trial_steps real steps (at least one
  * sort cycle) for each candidate -- push blocks per CU in {1,2,3,4,6,8}, the
  * XCD-aware tile walk on/off, sort_interval in {10,25,50,100} -- one knob at a
- * time, and keeps the fastest.  The trial steps advance the simulation; the
+ * time, and keeps the fastest; a block count other than the starting one must
+ * beat it again when the two are timed alternately twice.  The trial steps
+ * advance the simulation; the
  * physics does not depend on these choices (particle order and launch shape do
  * not change any result).  Errors: EINVAL, ESTATE, ECAPACITY, ENONFINITE. */
 int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out);
