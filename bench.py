@@ -358,6 +358,10 @@ def main():
                     help="eager steps with per-kernel events after the timed region")
     ap.add_argument("--backend", default="table", choices=["table", "exact", "off"])
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1"])
+    ap.add_argument("--eta-min", type=float, default=None,
+                    help="drag-time variant: eta_min instead of the workload's 1e3 (App. C uses 1e2)")
+    ap.add_argument("--mass-ratio", type=float, default=None,
+                    help="mass-ratio variant: m_i/m_e instead of the workload's 100")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -391,6 +395,13 @@ def main():
         return
     cfg = dict(workloads.CFG2 if args.workload == "cfg2" else workloads.CFG1)
     cfg["rics"] = args.backend
+    variant = ""
+    if args.eta_min is not None:
+        cfg["eta_min"] = args.eta_min
+        variant += f", eta_min={args.eta_min:g}"
+    if args.mass_ratio is not None:
+        cfg["mass_ratio"] = args.mass_ratio
+        variant += f", m_i/m_e={args.mass_ratio:g}"
     sim = Pic1D(cfg, device="cuda:0")
     print(f"# init done: {cfg['lines'][0]}", file=sys.stderr, flush=True)
     tune = sim.autotune(trial_steps=10)        # launch shape and sort interval (results do not depend on them)
@@ -402,7 +413,8 @@ def main():
     rp = timed_run(sim, args.profile_steps, 0, profile=True)
     bytes_per_launch = hbm_bytes_per_launch(rp)
     achieved = bytes_per_launch / rp["push_avg_s"]
-    traffic = measured_traffic(args.backend, args.workload)     # HBM bytes per k_push launch (rocprofv3)
+    # HBM bytes per k_push launch (rocprofv3), measured on the unmodified workload only
+    traffic = measured_traffic(args.backend, args.workload) if not variant else None
     m0, m1 = r["m0"], r["m1"]
     res = {
         "metric": "particle-steps/s (push+RICS drag+deposit+pairs)",
@@ -417,9 +429,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 particles / f64 field",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: one dipole line R_max=30, 65536 cells, 200 ppc e-/e+, "
-                               f"atmosphere ions m_i/m_e=100, pairs (curvature), {args.backend} RICS"
-                   if args.workload == "cfg2" else f"cfg1: R_max=4, 512 cells, 64 ppc, {args.backend} RICS",
+        "config": {"workload": (f"{args.workload}: one dipole line R_max=30, 65536 cells, 200 ppc e-/e+, "
+                                f"atmosphere ions m_i/m_e=100, pairs (curvature), {args.backend} RICS"
+                                if args.workload == "cfg2" else f"cfg1: R_max=4, 512 cells, 64 ppc, {args.backend} RICS")
+                               + variant,
                    "particles_start": sum(m0["count"]), "particles_end": sum(m1["count"]),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
