@@ -188,13 +188,15 @@ def test_annihilation_holds_cells_at_the_limit_independently_of_sorting():
     """With n_max below the initial density: pairs annihilate every step, every cell
     that keeps both e- and e+ ends each step at or below n_max, Gauss's law holds,
     and the result does not depend on the particle order (sorted every step, every
-    3 steps, never)."""
+    3 steps, never) nor on replaying the steps from captured graphs."""
     # (no atmosphere: on a line this short its layer fills every cell far beyond n_max)
     base = workloads.small(n_cells=96, ppc=20, rics="exact", pairs=True, nmax_over_n0=1.2)
     n_max = 1.2 * 20
     finals = []
-    for interval in (0, 1, 3):
+    for interval, graph in ((0, 0), (1, 0), (3, 0), (3, 6)):
         sim = _sim(dict(base, sort_interval=interval))
+        if graph:
+            sim.set_graph(graph)
         for _ in range(3):
             sim.step(4)
             P = [sim.get_particles(0, s) for s in range(4)]
@@ -210,7 +212,7 @@ def test_annihilation_holds_cells_at_the_limit_independently_of_sorting():
             o = np.argsort(Q["id"])
             out[s] = {k: v[o] for k, v in Q.items()}
         finals.append((out, sim.get_field(0)))
-        _print("sort interval", interval, "annihilated", m["counters"]["annihilated"])
+        _print("sort interval", interval, "graph", graph, "annihilated", m["counters"]["annihilated"])
     for out, E in finals[1:]:
         for s in range(4):
             for k in ("id", "cell", "off", "u"):
