@@ -64,8 +64,8 @@ def test_atmosphere_layer_is_topped_up_to_the_hydrostatic_profile():
 
 
 def _event_case(u0, x0=3.3, b_pole=10.0):
-    """One positron at x0 in the stochastic regime, field-free, with immediate pair
-    conversion; returns (state before, state after, the line)."""
+    """One positron (id 12345) at x0 in the stochastic regime, field-free, with
+    immediate pair conversion; returns (state, config)."""
     cfg = pic.make_config(lines=[dict(r_eq=4.0, n_cells=64, ppc_init=0, init="empty")], rics="exact",
                           j_twist=0.0, pairs=True, conversion="immediate", b_pole=b_pole, seed=5)
     st = pic.init_state(cfg)
@@ -115,3 +115,31 @@ def test_event_and_pair_conserve_energy(sign):
     assert math.copysign(1.0, ue) == sign and math.copysign(1.0, upos) == sign
     assert float(P[0]["x"][0]) == pytest.approx(x0, abs=1e-15)
     assert float(P[1]["x"][~parent][0]) == pytest.approx(x0, abs=1e-15)
+
+
+def test_event_and_pair_yield_follow_the_probability():
+    # Sec. 3: each lepton-step scatters with probability p = Ndot h (clipped at 1),
+    # decided by an independent uniform draw per particle and step.  N identical
+    # positrons with p ~ 0.3 give Binomial(N, p) events; with immediate conversion,
+    # eps >= 2 and n_max far away, every event makes one pair.
+    st0, cfg = _event_case(1.0)
+    ln = st0.lines[0]
+    x0 = 3.3
+    b, mu, xr, rc = ln.geometry_at(np.array([x0]))
+    _, _, rate = ln.rics_funcs(np.array([x0]), b, mu, xr)
+    us = np.sqrt(np.geomspace(3.0, 1e7, 2000) ** 2 - 1.0)
+    p_all = rate(us) * ln.h
+    ok = (p_all > 0.2) & (p_all < 0.4) & (rics.photon_energy(us, np.full(us.shape, b[0])) >= 2.0)
+    if not ok.any():
+        pytest.skip("no momentum with p in (0.2, 0.4) at this position")
+    u0 = float(us[np.nonzero(ok)[0][0]])
+    p = float(rate(np.array([u0]))[0] * ln.h)
+    n = 40000
+    st = pic.init_state(cfg)
+    pic.load_particles(st, 0, 1, np.full(n, 3, dtype=np.int32), np.full(n, x0 - 3.0), np.full(n, u0),
+                       np.arange(n, dtype=np.uint64) * 7 + 11)
+    pic.step(st)
+    ev = st.counters[0]["events"]
+    assert abs(ev - n * p) < 4.0 * math.sqrt(n * p * (1.0 - p))
+    assert st.counters[0]["pairs_created"] == ev
+    assert st.parts[0][0]["x"].size == ev
