@@ -39,13 +39,17 @@ post-kick momentum, recoil, move -- is a reading, the paper being silent):
   9. pair annihilation at the density limit n_max (see `annihilate`);
  10. Ampere  E_{k+1/2} -= 4 pi (j_{k+1/2} - j_psi).
 
-Pins: tests/test_oracle_pic.py (hyperbolic motion, Gauss's law to roundoff,
-energy ledger with drag off, cold two-stream growth rate) and
-tests/test_oracle_annihilation.py (the current of one annihilated pair in closed
-form, Gauss's law, the count left in a cell, independence of the particle order).  The atmosphere
-and pair-yield statistics are "parity unpinned" beyond Gauss neutrality and
-agreement with the GPU path; the event kinematics choice is pinned only by the
-photon-energy identities of rics.py.
+Pins:
+  * tests/test_oracle_pic.py: hyperbolic motion, Gauss's law to roundoff, the
+    energy ledger with drag off, the cold two-stream growth rate;
+  * tests/test_oracle_annihilation.py: the current of one annihilated pair in
+    closed form, Gauss's law, the count left in a cell, independence of the
+    particle order;
+  * tests/test_oracle_atmosphere_events.py: the refill's Maxwellian momenta,
+    uniform offsets and hydrostatic targets; energy conservation through an
+    event and its pair; the event and pair yield against Binomial(N, Ndot h).
+The photon energy eps itself is "parity unpinned" beyond the identities of
+rics.py: energy conservation pins what an event does with eps, not its formula.
 """
 import math
 
