@@ -123,6 +123,7 @@ __device__ __forceinline__ Geo geo_at(const LineDev& L, const float4* __restrict
 struct PartGeo {
     Geo g;
     TabRows rows;
+    TabMemo memo;
 };
 
 // The line's table and its second row (row j0 + 1 at the same byte offset).
@@ -132,10 +133,10 @@ __device__ __forceinline__ const char* tab_base(const PushArgs& a, const LineDev
 
 // F_hat at u with what dF/du needs (evaluated only where the midpoint asks for it).
 template <int BACKEND>
-__device__ __forceinline__ auto rics_eval(const PushArgs& a, const LineDev& L, float u, const PartGeo& pg) {
+__device__ __forceinline__ auto rics_eval(const PushArgs& a, const LineDev& L, float u, PartGeo& pg) {
     if constexpr (BACKEND == RICS_TABLE) {
         const char* tb = tab_base(a, L);
-        return table_eval(L, tb, tb + 16 * a.nlg, a.nlg, pg.rows, u);
+        return table_eval(L, tb, tb + 16 * a.nlg, a.nlg, pg.rows, u, pg.memo);
     } else {
         return exact_eval(L, u, pg.g);
     }
@@ -144,10 +145,10 @@ __device__ __forceinline__ float eval_dF(const LineDev& L, const TableEval& e) {
 __device__ __forceinline__ float eval_dF(const LineDev&, const ExactEval& e) { return e.dF(); }
 
 template <int BACKEND>
-__device__ __forceinline__ float rics_N(const PushArgs& a, const LineDev& L, float u, const PartGeo& pg) {
+__device__ __forceinline__ float rics_N(const PushArgs& a, const LineDev& L, float u, PartGeo& pg) {
     if constexpr (BACKEND == RICS_TABLE) {
         const char* tb = tab_base(a, L);
-        return table_N(L, tb, tb + 16 * a.nlg, a.nlg, pg.rows, u);
+        return table_N(L, tb, tb + 16 * a.nlg, a.nlg, pg.rows, u, pg.memo);
     } else {
         return exact_N(L, u, pg.g);
     }
@@ -168,7 +169,7 @@ __device__ __forceinline__ PartGeo part_geo(const PushArgs& a, const LineDev& L,
 // (kept out of line: it is rarely needed at these step sizes).
 template <int BACKEND>
 __device__ __forceinline__ float newton_midpoint(const PushArgs& a, const LineDev& L, float u0, float F0, float u1,
-                                              const PartGeo& g) {
+                                              PartGeo& g) {
     const float hq = 0.25f * L.h;
 #pragma unroll 1
     for (int it = 0; it < 4; ++it) {
@@ -186,7 +187,7 @@ __device__ __forceinline__ float newton_midpoint(const PushArgs& a, const LineDe
 // the predicted correction (h/4)|F'|(h/2)|F0| exceeds half an ulp of the result --
 // and exponential relaxation towards p_tilde = mu / (1 - mu^2)^(1/2) otherwise.
 template <int BACKEND>
-__device__ __forceinline__ float drag_half(const PushArgs& a, const LineDev& L, float u0, const PartGeo& g,
+__device__ __forceinline__ float drag_half(const PushArgs& a, const LineDev& L, float u0, PartGeo& g,
                                            float ptilde, bool alive, int& n_limited, int& n_newton) {
     const auto e0 = rics_eval<BACKEND>(a, L, u0, g);
     const float F0 = e0.F;
@@ -376,6 +377,7 @@ struct CellCache {
     float4 n0, n1;          // geometry nodes c, c+1
     TabRows rows0;
     bool rows_simple;
+    TabMemo memo;           // the lane's last table record (reset per tile)
 };
 
 template <int BACKEND>
@@ -419,7 +421,7 @@ __device__ __forceinline__ void cache_load(CellCache& cc, const PushArgs& a, con
 // cell (unsigned by the charge; jm and jp vanish unless the path leaves the cell).
 template <int BACKEND>
 __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDev& L, const TileCtx& T,
-                                                 const CellCache& cc, bool alive, int line, int sp, int64_t k,
+                                                 CellCache& cc, bool alive, int line, int sp, int64_t k,
                                                  int c0, float o0, float& u, Counts& cnt, int& c1, float& o1,
                                                  int& jm, int& j0, int& jp, int& d, bool& gone, const bf16x8* W,
                                                  const float* Wb) {
@@ -455,6 +457,7 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
         PartGeo pg;
         pg.g = geo_lerp(L, cc.n0, cc.n1, o0);
         if constexpr (BACKEND == RICS_TABLE) {
+            pg.memo = cc.memo;
             if (cc.rows_simple) {
                 pg.rows.pos.off = cc.rows0.pos.off;
                 pg.rows.pos.wj = fmaf(o0, L.s_scale_f, cc.rows0.pos.wj);
@@ -475,6 +478,7 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
             u += kick;
             if (alive) u = stochastic_step(a, L, T, line, k, c0, o0, u, pg.g, rics_N<BACKEND>(a, L, u, pg), cnt);
         }
+        if constexpr (BACKEND == RICS_TABLE) cc.memo = pg.memo;
     } else {
         u += kick;
     }
@@ -1786,7 +1790,7 @@ __global__ __launch_bounds__(256) void k_rics_eval(PushArgs a, int line, int64_t
     const float s = fminf(fmaxf(s_cells[i], 0.0f), (float)L.n_cells);
     const int c0 = min((int)floorf(s), L.n_cells - 1);
     const float o0 = s - (float)c0;
-    const PartGeo pg = part_geo<BACKEND>(a, L, a.nodes[L.node_base + c0], a.nodes[L.node_base + c0 + 1], c0, o0);
+    PartGeo pg = part_geo<BACKEND>(a, L, a.nodes[L.node_base + c0], a.nodes[L.node_base + c0 + 1], c0, o0);
     const Geo& g = pg.g;
     const float u = uin[i];
     float f = 0.0f, nd = 0.0f;

@@ -134,15 +134,32 @@ __device__ __forceinline__ TabCol table_col(const LineDev& L, int nlg, float ua)
     return c;
 }
 
+// The last table record a lane read: its byte offset (row j0, column i0, half)
+// and the two row pairs.  Consecutive evaluations of a lane often read the same
+// record (particles of one cell at similar gamma); they reuse it without a load.
+struct TabMemo {
+    uint32_t o = 0xffffffffu;
+    float2 a, b;
+};
+
 // The table is stored as [ns][nlg] float4 {F(i), F(i+1), Ndot(i), Ndot(i+1)} so that
 // one gather per row brings both columns of a quantity.  tb is the line's table,
 // tb1 = tb + nlg * 16 bytes (row j0 + 1 at the same offset).
 template <int HALF>      // 0: F, 1: Ndot
 __device__ __forceinline__ float2 table_pair(const char* __restrict__ tb, const char* __restrict__ tb1,
-                                             const TabRow& rw, const TabCol& cl, float& slope) {
+                                             const TabRow& rw, const TabCol& cl, float& slope, TabMemo& m) {
     const uint32_t o = (uint32_t)rw.off + ((uint32_t)cl.i0 << 4) + 8u * HALF;
-    const float2 a = *reinterpret_cast<const float2*>(tb + o);      // row j0
-    const float2 b = *reinterpret_cast<const float2*>(tb1 + o);     // row j0 + 1
+    float2 a, b;
+    if (o == m.o) {
+        a = m.a;
+        b = m.b;
+    } else {
+        a = *reinterpret_cast<const float2*>(tb + o);      // row j0
+        b = *reinterpret_cast<const float2*>(tb1 + o);     // row j0 + 1
+        m.o = o;
+        m.a = a;
+        m.b = b;
+    }
     const float fa = fmaf(rw.wj, b.x - a.x, a.x);                    // at column i0
     const float fc = fmaf(rw.wj, b.y - a.y, a.y);                    // at column i0 + 1
     slope = fc - fa;
@@ -161,11 +178,11 @@ struct TableEval {
 };
 
 __device__ __forceinline__ TableEval table_eval(const LineDev& L, const char* tb, const char* tb1, int nlg,
-                                                const TabRows& rows, float u) {
+                                                const TabRows& rows, float u, TabMemo& m) {
     TableEval e;
     e.ua = fabsf(u);
     const TabCol cl = table_col(L, nlg, e.ua);
-    const float2 f = table_pair<0>(tb, tb1, u < 0.0f ? rows.neg : rows.pos, cl, e.slope);
+    const float2 f = table_pair<0>(tb, tb1, u < 0.0f ? rows.neg : rows.pos, cl, e.slope, m);
     const float F = fmaf(cl.wi, e.slope, f.x);
     e.F = u < 0.0f ? -F : F;
     e.g2 = cl.g2;
@@ -174,10 +191,10 @@ __device__ __forceinline__ TableEval table_eval(const LineDev& L, const char* tb
 }
 
 __device__ __forceinline__ float table_N(const LineDev& L, const char* tb, const char* tb1, int nlg,
-                                         const TabRows& rows, float u) {
+                                         const TabRows& rows, float u, TabMemo& m) {
     const TabCol cl = table_col(L, nlg, fabsf(u));
     float slope;
-    const float2 n = table_pair<1>(tb, tb1, u < 0.0f ? rows.neg : rows.pos, cl, slope);
+    const float2 n = table_pair<1>(tb, tb1, u < 0.0f ? rows.neg : rows.pos, cl, slope, m);
     return fmaf(cl.wi, slope, n.x);
 }
 
