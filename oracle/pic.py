@@ -48,8 +48,9 @@ Pins:
   * tests/test_oracle_atmosphere_events.py: the refill's Maxwellian momenta,
     uniform offsets and hydrostatic targets; energy conservation through an
     event and its pair; the event and pair yield against Binomial(N, Ndot h).
-The photon energy eps itself is "parity unpinned" beyond the identities of
-rics.py: energy conservation pins what an event does with eps, not its formula.
+The photon energy eps is pinned in tests/test_oracle_rics.py by explicit
+four-momenta (resonant absorption, perpendicular decay, boost back);
+energy conservation through an event pins what the step does with it.
 """
 import math
 

@@ -21,7 +21,8 @@ Pins (tests/test_oracle_rics.py): Wien maximum of g (Sec. 2.2 "g ~ 1.4"),
 the drag length ~200 cm and eta ~3.8e4 at x = 10, kT = 1 keV (Sec. 2.2),
 F = Ndot * DeltaP (Sec. 2.2) and the attractor beta = mu, the photon-energy
 limits and bounds (Sec. 2.1, Appendix A.3), the excitation kinematics
-(Appendix A.1, Eq. excitedgamma) and a numerical quadrature of the rate
+(Appendix A.1, Eq. excitedgamma), eps and excited_gamma rebuilt from
+Lorentz boosts of four-momenta (Appendix A.1-A.3), and a numerical quadrature of the rate
 integral with a finite-width resonance that converges to the closed form.
 """
 import numpy as np

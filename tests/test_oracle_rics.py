@@ -2,6 +2,7 @@
 Appendix A, and a quadrature of the rate integral."""
 import json
 import os
+import math
 
 import numpy as np
 import pytest
@@ -195,3 +196,51 @@ def test_table_interpolation_error_shrinks_with_resolution():
         errs.append(np.max(np.abs(rics.table_lookup(F, N, u, xs, L)[1] / ex - 1)))
     assert errs[0] > errs[1] > errs[2]
     assert errs[0] / errs[2] > 8.0
+
+
+def _boost_photon_energy(gam, b):
+    """Photon energy and recoil gamma of one resonant scattering from four-momenta
+    (m_e = c = 1, momenta along B): a soft photon met head-on is absorbed when the
+    pair's invariant mass reaches E_B = (1 + 2b)^(1/2) (Eq. elandau); in the rest frame
+    of the excited state the photon leaves perpendicular to B, so the lepton keeps no
+    parallel momentum there and drops to the ground level at rest (energy 1), the
+    photon taking E_B - 1; both are boosted back along B with the excited state's
+    rapidity.  Returns (photon energy, lepton gamma, absorbed photon energy), all lab."""
+    p = math.sqrt(gam * gam - 1.0)
+    eb = math.sqrt(1.0 + 2.0 * b)
+    # invariant mass^2 of (gam, p) + (k, -k) is 1 + 2 k (gam + p): solve for k by bisection
+    lo, hi = 0.0, 1.0
+    while 1.0 + 2.0 * hi * (gam + p) < eb * eb:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if 1.0 + 2.0 * mid * (gam + p) < eb * eb:
+            lo = mid
+        else:
+            hi = mid
+    k = 0.5 * (lo + hi)
+    # E - p_par and E + p_par of the sum, the first without cancellation (gam - p = 1/(gam + p))
+    minus, plus = 1.0 / (gam + p) + 2.0 * k, gam + p
+    assert math.sqrt(minus * plus) == pytest.approx(eb, rel=1e-12)
+    y = 0.5 * math.log(plus / minus)
+    # rest-frame four-momenta (E, p_par): photon (eb - 1, 0), lepton (1, 0)
+    return math.cosh(y) * (eb - 1.0), math.cosh(y) * 1.0, k
+
+
+@pytest.mark.parametrize("b", [1e-3, 0.05, 1.0, 30.0])
+def test_photon_energy_from_lorentz_boosts(b):
+    # Appendix A.1-A.3 through explicit four-momenta rather than the closed form:
+    # the boosted photon energy equals photon_energy up to the neglected energy of
+    # the absorbed soft photon (relative k/gamma < b/gamma^2), and the boosted
+    # lepton's gamma equals gamma - eps to the same order
+    for gam in (50.0, 1e3, 1e5):
+        e_boost, g_boost, k = _boost_photon_energy(gam, b)
+        e = float(rics.photon_energy(math.sqrt(gam * gam - 1.0), b))
+        assert k / gam < b / gam ** 2
+        assert abs(e_boost / e - 1.0) <= 1.001 * k / gam + 1e-13
+        assert abs(g_boost - (gam - e)) <= 1.001 * k + 1e-13 * gam
+    # in the rest frame of the incoming lepton the absorbed photon has energy b and
+    # the excited state moves with the Lorentz factor of excited_gamma
+    e0, g0, k0 = _boost_photon_energy(1.0, b)
+    assert k0 == pytest.approx(b, rel=1e-12)
+    assert float(rics.excited_gamma(b)) == pytest.approx(g0, rel=1e-12)
