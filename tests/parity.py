@@ -155,8 +155,24 @@ def _child_parent_x(ocfg, step, parts_before):
     return out
 
 
-def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=None):
+def restrict(snap, keep):
+    """The snapshot with only the particles whose id is in keep (a uint64 array);
+    fields are kept whole."""
+    lines = []
+    for L in snap["lines"]:
+        parts = []
+        for P in L["parts"]:
+            m = np.isin(P["id"], keep)
+            parts.append({k: v[m] for k, v in P.items()})
+        lines.append(dict(parts=parts, E=L["E"]))
+    return dict(lines=lines, step=snap["step"])
+
+
+def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=None, check_field=True):
     """Advance the oracle from snap_before and compare with the GPU's snap_after.
+
+    With check_field False the field after Ampere is not compared (for a
+    sample of the particles, whose current is not the whole line's).
 
     Returns a report dict; raises AssertionError on an unexcused mismatch.
     """
@@ -309,6 +325,8 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
             rep["atm_cells_excused"] = sorted(atm_cells_excused)
             for c in atm_cells_excused:
                 assert min(c, n - 1 - c) < ln.atm_depth + 2, f"atmosphere mismatch outside the layer, cell {c}"
+        if not check_field:
+            continue
         # field after Ampere
         Eg = Lg["E"]
         Eo = st.E[li]
@@ -323,4 +341,32 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
             k = int(np.argmax(dE - tolE))
             raise AssertionError(f"line {li}: E mismatch at cell {k}: gpu {Eg[k]} oracle {Eo[k]} tol {tolE[k]}")
         rep["max_dE"] = max(rep["max_dE"], float((dE / (4 * math.pi * ln.Q)).max()))
+    return rep, st
+
+
+def sampled_compare(ocfg, snap_before, snap_after, n_sample, rng):
+    """compare_step on a sample of a full-size line (one line).
+
+    Given the field, a particle's push, drag, event and conversion do not depend on
+    the other particles, and the atmosphere refill depends only on the end-of-step
+    counts of the atmosphere species.  The sample is therefore every atmosphere
+    particle, n_sample seeded e-/e+ per lepton species, the pair members the sampled
+    leptons can create this step (ids from the child stream) and the atmosphere
+    particles injected this step.  The field after Ampere is not compared."""
+    L0, L1 = snap_before["lines"][0], snap_after["lines"][0]
+    keep = []
+    for s in range(4):
+        ids = L0["parts"][s]["id"]
+        keep.append(ids if s >= 2 or ids.size <= n_sample else rng.choice(ids, size=n_sample, replace=False))
+    parents = np.concatenate(keep[:3]).astype(np.uint64)
+    k0, k1 = philox.seed_key(ocfg["seed"])
+    lo, hi = philox.split_id(parents)
+    w = philox.philox4x32_10(snap_before["step"], lo, hi, philox.STREAM_CHILD, k0, k1)
+    children = [philox.id_from_words(w[0], w[1]), philox.id_from_words(w[2], w[3])]
+    injected = [np.setdiff1d(L1["parts"][s]["id"], L0["parts"][s]["id"]) for s in (2, 3)]
+    keep_before = np.unique(np.concatenate(keep).astype(np.uint64))
+    keep_after = np.unique(np.concatenate(keep + children + injected).astype(np.uint64))
+    rep, st = compare_step(ocfg, restrict(snap_before, keep_before), restrict(snap_after, keep_after),
+                           check_field=False)
+    rep["sampled"] = [int(k.size) for k in keep]
     return rep, st

@@ -143,6 +143,41 @@ def test_cfg1_hot_full_size_parity():
     assert m["gauss_residual"] <= 1e-6
 
 
+def test_cfg2_full_size_sampled_parity_and_ledger():
+    """The R_max = 30 line at full size (65,536 cells, 2.67e7 particles; table RICS,
+    atmosphere with ions at m_i/m_e = 100, pairs with curvature conversion) in the
+    launch shape the autotuner picks, as in the timed benchmark steps.  One step
+    after the tuner's trial steps is compared on a sample: every atmosphere particle,
+    40,000 e- and 40,000 e+, the pair members they can make and the atmosphere
+    particles injected in the step.  The whole line is checked through Gauss's law,
+    the particle-count ledger of the counters and the live counts read back."""
+    cfg = dict(workloads.CFG2)
+    ocfg = parity.oracle_config(cfg)
+    sim = _sim(cfg)
+    tune = sim.autotune(trial_steps=10)
+    _print("cfg2 autotune", tune)
+    sim.step(5)
+    m0 = sim.moments(0)
+    before = parity.snapshot(sim)
+    sim.step(1)
+    m1 = sim.moments(0)
+    after = parity.snapshot(sim)
+    d = {k: m1["counters"][k] - m0["counters"][k] for k in m0["counters"]}
+    _print("cfg2 step", m1["step"], m1["count"], d, m1["gauss_residual"])
+    # n_max = d0^2 n0 (460,800 per cell) is far above every cell's count
+    assert d["annihilated"] == 0
+    grown = 2 * (d["pairs_created"] + d["atm_injected"] - d["annihilated"]) - d["absorbed"]
+    assert sum(m1["count"]) - sum(m0["count"]) == grown
+    for s in range(4):
+        assert after["lines"][0]["parts"][s]["id"].size == m1["count"][s]
+    assert m1["count"][2] > 100000 and m1["count"][3] > 100000
+    assert m1["gauss_residual"] <= 1e-6
+    rep, _ = parity.sampled_compare(ocfg, before, after, 40000, np.random.default_rng(2))
+    _print("cfg2 sampled", rep)
+    assert rep["compared"] > 80000
+    assert rep["excused"] <= max(3, 1e-3 * rep["compared"])
+
+
 def test_cascade_gauss_and_counts_over_many_steps():
     cfg = workloads.small(n_cells=128, ppc=8, rics="exact", pairs=True, atmosphere=True,
                           conversion="curvature", sort_interval=3)
