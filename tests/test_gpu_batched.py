@@ -136,3 +136,54 @@ def test_many_lines_conserve_charge_per_line():
         assert m["step"] == 45
     _print("64 lines: worst Gauss residual", worst)
     assert worst <= 1e-6
+
+
+def _line_snapshot(sim, li):
+    m = sim.moments(li)
+    return dict(lines=[dict(parts=[sim.get_particles(li, s) for s in range(4)], E=sim.get_field(li))],
+                step=m["step"]), m
+
+
+def test_cfg3_full_size_sampled_lines_and_ledger():
+    """The 256-line batched workload at full size (about 2.3e6 cells and 6.6e8
+    particles) in the autotuned launch shape, replayed from 100-step HIP graphs as in
+    the timed benchmark.  After 100 replayed steps, one step is compared on the
+    shortest, the median and the longest line, each on a sample (every particle of a
+    line with at most 40,000 per species, else 40,000 e- and 40,000 e+, and the pair
+    members they can make) against a one-line oracle configuration: a line's step
+    does not depend on its place in the batch (event and pair draws are keyed by
+    step and particle id).  Every line is checked through Gauss's law and its
+    particle-count ledger."""
+    cfg = workloads.cfg3()
+    sim = Pic1D(cfg)
+    tune = sim.autotune(trial_steps=5)
+    _print("cfg3 autotune", tune)
+    sim.set_graph(100)
+    sim.step(100)
+    n = sim.n_lines
+    cells = np.array([l["n_cells"] for l in cfg["lines"]])
+    order = np.argsort(cells, kind="stable")
+    pick = [int(order[0]), int(order[n // 2]), int(order[-1])]
+    m0 = [sim.moments(li) for li in range(n)]
+    before = {li: _line_snapshot(sim, li)[0] for li in pick}
+    sim.step(1)
+    after = {}
+    worst = 0.0
+    for li in range(n):
+        if li in pick:
+            after[li], m1 = _line_snapshot(sim, li)
+        else:
+            m1 = sim.moments(li)
+        d = {k: m1["counters"][k] - m0[li]["counters"][k] for k in m1["counters"]}
+        grown = 2 * (d["pairs_created"] - d["annihilated"]) - d["absorbed"]
+        assert sum(m1["count"]) - sum(m0[li]["count"]) == grown, (li, d)
+        assert m1["step"] == m0[li]["step"] + 1
+        worst = max(worst, m1["gauss_residual"])
+    _print("cfg3 worst Gauss residual", worst)
+    assert worst <= 1e-6
+    for li in pick:
+        ocfg = parity.oracle_config(dict(cfg, lines=[cfg["lines"][li]]))
+        rep, _ = parity.sampled_compare(ocfg, before[li], after[li], 40000, np.random.default_rng(li))
+        _print("cfg3 line", li, cfg["lines"][li]["n_cells"], "cells:", rep)
+        assert rep["compared"] > 2000
+        assert rep["excused"] <= max(3, 1e-3 * rep["compared"])
