@@ -178,6 +178,46 @@ def test_cfg2_full_size_sampled_parity_and_ledger():
     assert rep["excused"] <= max(3, 1e-3 * rep["compared"])
 
 
+@pytest.mark.parametrize("rics", ["table", "exact"])
+def test_cfg4_full_size_density_limit_and_ledger(rics):
+    """The hot R_max = 4 line at full size (65,536 cells, 2.6e7 particles, immediate
+    conversion, n_max = 3 n_0 = 600 per cell) in the autotuned launch shape, once
+    the cascade has reached the density limit.  Which pairs annihilate depends on
+    every particle of a cell, so the step is checked through what the count rule
+    fixes at any size: every cell ends the step at or below n_max unless it has run
+    out of e- or e+; the particle-count ledger of the counters (with the annihilated
+    pairs) and the live counts hold; and Gauss's law holds."""
+    cfg = dict(workloads.CFG4, rics=rics)
+    sim = _sim(cfg)
+    _print("cfg4", rics, "autotune", sim.autotune(trial_steps=5))
+    d = None
+    for _ in range(40):
+        m0 = sim.moments(0)
+        sim.step(1)
+        m1 = sim.moments(0)
+        d = {k: m1["counters"][k] - m0["counters"][k] for k in m1["counters"]}
+        if d["annihilated"] > 0:
+            break
+        sim.step(9)
+    _print("cfg4 step", m1["step"], m1["count"], d, m1["gauss_residual"])
+    assert d["annihilated"] > 0 and d["pairs_created"] > 0
+    grown = 2 * (d["pairs_created"] + d["atm_injected"] - d["annihilated"]) - d["absorbed"]
+    assert sum(m1["count"]) - sum(m0["count"]) == grown
+    n = sim.n_cells(0)
+    per = []
+    for s in range(4):
+        P = sim.get_particles(0, s)
+        assert P["id"].size == m1["count"][s]
+        per.append(np.bincount(P["cell"], minlength=n))
+    N = per[0] + per[1] + per[2] + per[3]
+    n_max = cfg["nmax_over_n0"] * cfg["ppc0"]
+    bad = (N > n_max) & (per[0] > 0) & (per[1] > 0)
+    _print("cfg4 cells at the limit", int((N >= n_max - 1).sum()), "max count", int(N.max()))
+    assert not bad.any(), np.nonzero(bad)[0][:10]
+    assert (N >= n_max - 1).sum() > 0
+    assert m1["gauss_residual"] <= 1e-6
+
+
 def test_cascade_gauss_and_counts_over_many_steps():
     cfg = workloads.small(n_cells=128, ppc=8, rics="exact", pairs=True, atmosphere=True,
                           conversion="curvature", sort_interval=3)
