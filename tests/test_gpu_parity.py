@@ -408,7 +408,7 @@ def test_rics_eval_matches_oracle(backend):
     # inputs carry their rounding into F amplified by (gamma |mu| + |u|) / |gamma mu - u|
     gam = np.sqrt(1 + uu * uu)
     cond = (gam * np.abs(mu) + np.abs(uu)) / np.maximum(np.abs(gam * mu - uu), 1e-300)
-    relF_c = (np.abs(F - Fo) / np.abs(Fo) / (1.0 + 1e-2 * cond))[sig]
+    relF_c = np.abs(F - Fo)[sig] / np.abs(Fo)[sig] / (1.0 + 1e-2 * cond[sig])
     relF = np.abs(F - Fo)[sig] / np.abs(Fo)[sig]
     sigN = No * ln.h > 1e-9
     relN = np.abs(N - No)[sigN] / No[sigN]
