@@ -102,3 +102,36 @@ def test_nonfinite_momentum_freezes_the_state():
     assert STATUS[err2.value.code] == "ESTATE"
     m = sim.moments(0)               # still readable
     assert m["step"] >= 1
+
+
+def test_capacity_overflow_freezes_the_state():
+    # segments that start full (64 cells x 4 per cell = 256, the capacity) and are
+    # never compacted: the first pair created finds no slot, so the step fails with
+    # ECAPACITY without writing beyond the segment, the next call fails with ESTATE,
+    # and the state stays readable with every live particle inside the line
+    from paper_2609_17661_amd import Pic1dError
+    from paper_2609_17661_amd.pic1d import STATUS
+    cfg = workloads.small(r_eq=4.0, n_cells=64, ppc=4, init="hot", gamma_max=1e4, pairs=True,
+                          conversion="immediate", sort_interval=0, capacity=[256, 256, 0, 0])
+    sim = Pic1D(cfg)
+    code = None
+    for k in range(200):
+        try:
+            sim.step(1)
+        except Pic1dError as e:
+            code = STATUS[e.code]
+            break
+    print("capacity overflow at step", k, code, flush=True)
+    assert code == "ECAPACITY"
+    with pytest.raises(Pic1dError) as err2:
+        sim.step(1)
+    assert STATUS[err2.value.code] == "ESTATE"
+    m = sim.moments(0)
+    for s in (0, 1):
+        # the histogram count of a frozen state is not repaired after the overflow
+        # and may exceed the live particles; both stay within the capacity
+        P = sim.get_particles(0, s)
+        print("species", s, "histogram count", m["count"][s], "live", P["id"].size, flush=True)
+        assert 0 < P["id"].size <= m["count"][s] <= 256
+        assert np.unique(P["id"]).size == P["id"].size
+        assert np.all((P["cell"] >= 0) & (P["cell"] < 64))
