@@ -128,8 +128,9 @@ def test_capacity_overflow_freezes_the_state():
     assert STATUS[err2.value.code] == "ESTATE"
     m = sim.moments(0)
     for s in (0, 1):
-        # the histogram count of a frozen state is not repaired after the overflow
-        # and may exceed the live particles; both stay within the capacity
+        # once the error is flagged the step's remaining kernels return at once, so
+        # the frozen state holds the pushed particles (absorbed ones dead) with the
+        # histogram of the step's start: its count may exceed the live particles
         P = sim.get_particles(0, s)
         print("species", s, "histogram count", m["count"][s], "live", P["id"].size, flush=True)
         assert 0 < P["id"].size <= m["count"][s] <= 256
