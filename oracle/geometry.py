@@ -14,7 +14,9 @@ s = L at the southern one.  R = r_eq / R* ("R_max").
 Pins (tests/test_oracle_geometry.py): the line length against the paper's
 cell count N_x = 3.84e5 at dl/R* = 6.67e-5 for r_eq = 10 (Sec. 3 and 4.2),
 B at the pole surface = B*, mirror symmetry about the equator, mu = 0 and
-R_curv = R/3 at the equator, and a brute-force polyline arc length.
+R_curv = R/3 at the equator, and a brute-force polyline arc length;
+interp_nodes against numpy's piecewise-linear interp, at nodes and midpoints
+(tests/test_oracle_circuit_gravity.py).
 """
 import numpy as np
 

@@ -48,6 +48,14 @@ Pins:
   * tests/test_oracle_atmosphere_events.py: the refill's Maxwellian momenta,
     uniform offsets and hydrostatic targets; energy conservation through an
     event and its pair; the event and pair yield against Binomial(N, Ndot h).
+  * tests/test_oracle_circuit_gravity.py: the circuit potential V_c against the
+    energy a test lepton gains crossing a frozen-field line (sign and 1/c^2), and
+    the layer gravity against relativistic free fall under a constant force
+    towards the nearer wall (fall time from rest, apex of a thrown particle, no
+    force outside the layer).
+Parity unpinned: which e-/e+ of an over-full cell annihilate (the smallest Philox
+keys) is a reading of a step the paper leaves open; it is pinned only by its
+independence of the particle order, not by anything the paper fixes.
 The photon energy eps is pinned in tests/test_oracle_rics.py by explicit
 four-momenta (resonant absorption, perpendicular decay, boost back);
 energy conservation through an event pins what the step does with it.
