@@ -49,9 +49,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 BF16_PEAK = 2.5e15         # MI355X dense bf16 MFMA, FLOP/s
+# algorithmic bytes of the particle kernel per particle-step: a lepton reads cell,
+# offset, momentum and id (16 B) and writes cell, offset, momentum (12 B); an ion
+# needs no id (no draws)
+BYTES_PER_LEPTON = 28
+BYTES_PER_ION = 24
+BYTES_PER_CREATED = 16     # a created particle written by the append kernel
+# the stricter count of what the kernel must move: the id is read only for a draw
 BYTES_PER_PARTICLE = 24    # cell, offset, u: read 12 B + write 12 B
 BYTES_PER_DRAW = 8         # 64-bit id read for a Philox event draw
-BYTES_PER_CHILD = 20       # appended particle: cell, offset, u, id
 MLP_FLOP_PER_EVAL = 2 * (4 * 128 + 3 * 128 * 128 + 128 * 3)   # multiply-adds of one network evaluation, x2
 MLP_MFMA_PER_GROUP = 308   # v_mfma_f32_16x16x32_bf16 per 16 evaluations (three bfloat16 terms per activation)
 PROFILE_HBM = os.path.join(ROOT, "profiles", "k_push_cfg2_table_hbm.md")
@@ -109,14 +115,15 @@ def copy_calibration():
           flush=True)
 
 
-def cpu_baseline(cfg, sample_ppc=40, steps=6):
-    """The oracle (FP64 numpy, single thread) on the same line with fewer particles per cell."""
+def _oracle_run(cfg, sample_ppc, steps, seed):
+    """Step the oracle (one thread of numpy) on the workload's first line with
+    sample_ppc pairs per cell; returns (particle-steps, seconds, particles at start)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import pic
     from tests import parity
 
-    c = dict(cfg)
+    c = dict(cfg, seed=seed)
     c["lines"] = [dict(cfg["lines"][0], ppc_init=sample_ppc)]
     ocfg = parity.oracle_config(c)
     st = pic.init_state(ocfg)
@@ -128,10 +135,58 @@ def cpu_baseline(cfg, sample_ppc=40, steps=6):
             pushed += sum(p["x"].size for p in st.parts[0])
             pic.step(st)
         dt = time.perf_counter() - t0
-    return dict(value=pushed / dt, unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"R_max=30 line, 65,536 cells, {sample_ppc} e-/e+ per cell ({n0} particles) "
-                       f"+ atmosphere and pairs as in the workload, {steps} steps, numpy float64, one thread",
-                seconds=dt)
+    return pushed, dt, n0
+
+
+def _oracle_worker(args):
+    import threadpoolctl  # noqa: F401  (imported before numpy spins up its pools)
+    cfg, sample_ppc, steps, seed = args
+    return _oracle_run(cfg, sample_ppc, steps, seed)
+
+
+def cpu_baseline(cfg, sample_ppc=40, steps=6):
+    """The oracle (FP64 numpy) on the same line with fewer particles per cell: one
+    process on one core, then one process per host core, each stepping its own
+    copy of the line (different seeds; lines are independent), timed together."""
+    import multiprocessing as mp
+
+    pushed, dt, n0 = _oracle_run(cfg, sample_ppc, steps, cfg.get("seed", 0))
+    single = dict(value=pushed / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                  sample=f"R_max=30 line, 65,536 cells, {sample_ppc} e-/e+ per cell ({n0} particles) "
+                         f"+ atmosphere and pairs as in the workload, {steps} steps, numpy float64, one thread",
+                  seconds=dt)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(cfg, sample_ppc, steps, 1000 + k) for k in range(cores)])
+    wall = time.perf_counter() - t0
+    # timed from the slowest worker's own clock (process start-up excluded)
+    tot = sum(r[0] for r in res)
+    slowest = max(r[1] for r in res)
+    single["all_cores"] = dict(value=tot / slowest, unit="particle-steps/s", cores=cores, kind="oracle",
+                               sample=f"{cores} processes, each the single-thread sample on its own copy of "
+                                      f"the line (seeds 1000+k)", seconds=slowest, wall_seconds=wall)
+    single["host"] = _host_cpu()
+    return single
+
+
+def _host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def _counters(sim):
@@ -191,9 +246,39 @@ def pick_launch(sim, trial_steps=200, graph_steps=100):
 
 
 def hbm_bytes_per_launch(r):
+    """Algorithmic bytes of one particle-kernel launch: 28 B per lepton-step, 24 B
+    per ion-step."""
     c = r["counters"]
-    return (BYTES_PER_PARTICLE * c["pushed"] + BYTES_PER_DRAW * c["draws"] +
-            BYTES_PER_CHILD * 2 * c["pairs_created"]) / max(r["launches"], 1)
+    ions = c["pushed_ions"]
+    return (BYTES_PER_LEPTON * (c["pushed"] - ions) + BYTES_PER_ION * ions) / max(r["launches"], 1)
+
+
+def strict_bytes_per_launch(r):
+    """What the kernel must move at the least: cell, offset and momentum both ways,
+    the id only where a draw needs it."""
+    c = r["counters"]
+    return (BYTES_PER_PARTICLE * c["pushed"] + BYTES_PER_DRAW * c["draws"]) / max(r["launches"], 1)
+
+
+def window_bytes(r):
+    """Algorithmic bytes of all steps of a window: the particle kernel's plus 16 B
+    per created particle (pair members and atmosphere particles)."""
+    c = r["counters"]
+    ions = c["pushed_ions"]
+    created = 2 * c["pairs_created"] + 2 * c["atm_injected"]
+    return BYTES_PER_LEPTON * (c["pushed"] - ions) + BYTES_PER_ION * ions + BYTES_PER_CREATED * created
+
+
+def push_roofline(r):
+    b = hbm_bytes_per_launch(r)
+    achieved = b / r["push_avg_s"]
+    strict = strict_bytes_per_launch(r)
+    return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "kernel": "k_push", "avg_ms": r["push_avg_s"] * 1e3,
+            "launches": r["launches"], "bytes_per_launch": b,
+            "bytes_rule": "28 B per lepton-step, 24 B per ion-step",
+            "strict_bytes_per_launch": strict, "strict_frac": strict / r["push_avg_s"] / HBM_PEAK,
+            "strict_rule": "24 B per particle-step + 8 B per Philox draw (id read only for a draw)"}
 
 
 def surrogate_comparison(steps, warmup, mlp_steps):
@@ -217,17 +302,30 @@ def surrogate_comparison(steps, warmup, mlp_steps):
             cfg["mlp_params"] = tr["params"]
             cfg["mlp_norm"] = tr["norm"]
         sim = Pic1D(cfg, device="cuda:0")
+        # the same steps for every backend: the cascade reaches the density limit within
+        # its first tens of steps, and the warm-up puts the timed steps there (sorted
+        # every 5 steps, the autotuner's choice on this line)
         r = timed_run(sim, steps, warmup)
+        c = r["counters"]
         entry = {"value": r["value"], "ms_per_step": r["ms_per_step"], "k_push_ms": r["push_avg_s"] * 1e3,
-                 "kernels_ms": r["kernels_ms"], "events": r["counters"]["events"],
-                 "pairs_created": r["counters"]["pairs_created"]}
+                 "kernels_ms": r["kernels_ms"], "events_per_step": c["events"] / steps,
+                 "pairs_created_per_step": c["pairs_created"] / steps,
+                 "annihilated_per_step": c["annihilated"] / steps, "particles_end": sum(r["m1"]["count"]),
+                 "step_window": [r["m0"]["step"], r["m1"]["step"]]}
+        if backend != "mlp":
+            entry["roofline"] = push_roofline(r)
         if backend == "mlp":
-            evals = r["counters"]["mlp_evals"] / max(r["launches"], 1)
-            achieved = evals * MLP_FLOP_PER_EVAL / r["push_avg_s"]
-            executed = evals / 16 * MLP_MFMA_PER_GROUP * (16 * 16 * 32 * 2) / r["push_avg_s"]
+            launches = max(r["launches"], 1)
+            needed = c["mlp_needed"] / launches
+            lanes = c["mlp_evals"] / launches
+            achieved = needed * MLP_FLOP_PER_EVAL / r["push_avg_s"]
+            executed = lanes / 16 * MLP_MFMA_PER_GROUP * (16 * 16 * 32 * 2) / r["push_avg_s"]
             entry["roofline"] = {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12,
                                  "unit": "TFLOP/s", "frac": achieved / BF16_PEAK, "kernel": "k_push<mlp>",
-                                 "evals_per_launch": evals, "flop_per_eval": MLP_FLOP_PER_EVAL,
+                                 "evals_needed_per_launch": needed, "flop_per_eval": MLP_FLOP_PER_EVAL,
+                                 "rule": "evaluations the step needs: 2 per continuous-regime lepton step "
+                                         "plus its refinements, 1 per stochastic-regime step",
+                                 "lane_evals_executed_per_launch": lanes,
                                  "executed_mfma_tflops": executed / 1e12, "executed_frac": executed / BF16_PEAK}
             # network error against the library's exact backend at this workload's particles
             p = sim.get_particles(0, 0)
@@ -260,7 +358,8 @@ def surrogate_comparison(steps, warmup, mlp_steps):
         print(f"# {backend}: {entry['value']:.3g} particle-steps/s", file=sys.stderr, flush=True)
     out.update(res)
     out["workload"] = ("cfg4: R_max=4 line (the network's training geometry), 65536 cells, 200 hot e-/e+ per cell "
-                       "(gamma log-uniform to 1e4), pairs (immediate)")
+                       "(gamma log-uniform to 1e4), pairs (immediate) held by n_max = 3 n0, sorted every 5 steps; "
+                       "every backend timed over the same steps after the same warm-up")
     out["mlp_over_table"] = res["mlp"]["value"] / res["table"]["value"]
     return out
 
@@ -282,16 +381,13 @@ def batched_path(steps, warmup):
     rp = timed_run(sim, 10, 0, profile=True)         # kernel breakdown (eager launches)
     gauss = [sim.moments(li)["gauss_residual"] for li in range(sim.n_lines)]
     counts = sum(sum(sim.moments(li)["count"]) for li in range(sim.n_lines))
-    bytes_per_launch = hbm_bytes_per_launch(rp)
     out = {"workload": f"cfg3: {sim.n_lines} lines, R_max log-uniform in [2, 100], "
                        f"{sum(l['n_cells'] for l in cfg['lines'])} cells, 32-256 e-/e+ per cell per line, "
                        "cold, table RICS, pairs (curvature), sort every 50 steps (tuned)",
            "value": r["value"], "ms_per_step": r["ms_per_step"], "steps": steps, "launch": launch,
            "particles": counts, "autotune": tune, "init_seconds": t_init,
            "eager_ms_per_step": rp["ms_per_step"], "kernels_ms": rp["kernels_ms"],
-           "roofline": {"bound": "hbm", "achieved": bytes_per_launch / rp["push_avg_s"] / 1e9,
-                        "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                        "frac": bytes_per_launch / rp["push_avg_s"] / HBM_PEAK, "kernel": "k_push"},
+           "roofline": push_roofline(rp),
            "gauss_residual_max_over_lines": max(gauss)}
     sim.close()
     del sim
@@ -349,6 +445,53 @@ def cascade_run(chunks, chunk_steps, profile_steps):
     return out
 
 
+def plain_path(cfg, steps, warmup, profile_steps):
+    """Autotune, pick eager or graph launches, time `steps` steps after `warmup`,
+    then a profiled window of eager launches for the kernel breakdown."""
+    from paper_2609_17661_amd import Pic1D
+
+    sim = Pic1D(cfg, device="cuda:0")
+    print(f"# init done: {cfg['lines'][0]}", file=sys.stderr, flush=True)
+    tune = sim.autotune(trial_steps=10)        # launch shape and sort interval (results do not depend on them)
+    print(f"# autotuned: {tune}", file=sys.stderr, flush=True)
+    launch = pick_launch(sim)
+    print(f"# launch: {launch}", file=sys.stderr, flush=True)
+    r = timed_run(sim, steps, warmup, profile=False)
+    # kernel breakdown and roofline: events around every launch, eager launches
+    rp = timed_run(sim, profile_steps, 0, profile=True)
+    sim.close()
+    del sim
+    return r, rp, tune, launch
+
+
+def whole_step(r, steps):
+    """Algorithmic bytes of whole steps (particle kernel plus created particles) over
+    the timed window's step time: the roofline of the step, sorts and all."""
+    b = window_bytes(r) / steps
+    t = r["ms_per_step"] * 1e-3
+    return {"bytes_per_step": b, "achieved": b / t / 1e9, "unit": "GB/s", "frac": b / t / HBM_PEAK}
+
+
+def active_phase(cfg, steps, warmup, profile_steps):
+    """The headline line with a hot pair plasma (gamma log-uniform to 1e4): RICS
+    events, drag on both branches and pair creation act in every timed step."""
+    c = dict(cfg)
+    c["lines"] = [dict(cfg["lines"][0], init="hot", init_gamma_max=1.0e4)]
+    r, rp, tune, launch = plain_path(c, steps, warmup, profile_steps)
+    cnt = r["counters"]
+    out = {"workload": "cfg2 line (R_max=30, 65536 cells, 200 ppc, atmosphere, pairs by curvature conversion), "
+                       "hot start: gamma log-uniform in [1, 1e4]",
+           "value": r["value"], "unit": "particle-steps/s", "ms_per_step": r["ms_per_step"],
+           "step_window": [r["m0"]["step"], r["m1"]["step"]],
+           "events_per_step": cnt["events"] / steps, "pairs_created_per_step": cnt["pairs_created"] / steps,
+           "draws_per_step": cnt["draws"] / steps, "newton_per_step": cnt["newton"] / steps,
+           "particles_end": sum(r["m1"]["count"]), "roofline": push_roofline(rp),
+           "whole_step": whole_step(r, steps), "kernels_ms": rp["kernels_ms"], "autotune": tune, "launch": launch,
+           "gauss_residual": r["m1"]["gauss_residual"]}
+    print(f"# active phase: {out['value']:.3g} particle-steps/s", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,7 +500,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100,
                     help="eager steps with per-kernel events after the timed region")
     ap.add_argument("--backend", default="table", choices=["table", "exact", "off"])
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1", "cfg4"])
+    ap.add_argument("--init", default=None, choices=["cold", "hot"],
+                    help="initial plasma of the line instead of the workload's (hot: gamma log-uniform to 1e4)")
+    ap.add_argument("--no-active", action="store_true", help="skip the hot-start leg of the headline line")
     ap.add_argument("--eta-min", type=float, default=None,
                     help="drag-time variant: eta_min instead of the workload's 1e3 (App. C uses 1e2)")
     ap.add_argument("--mass-ratio", type=float, default=None,
@@ -390,10 +536,10 @@ def main():
         print(json.dumps({"cascade": cascade_run(args.cascade_chunks, 100, 20)}), flush=True)
         return
     if args.surrogate_only:
-        print(json.dumps({"surrogate_vs_table": surrogate_comparison(args.surrogate_steps, 3, args.mlp_train_steps)}),
+        print(json.dumps({"surrogate_vs_table": surrogate_comparison(args.surrogate_steps, 30, args.mlp_train_steps)}),
               flush=True)
         return
-    cfg = dict(workloads.CFG2 if args.workload == "cfg2" else workloads.CFG1)
+    cfg = dict({"cfg2": workloads.CFG2, "cfg1": workloads.CFG1, "cfg4": workloads.CFG4}[args.workload])
     cfg["rics"] = args.backend
     variant = ""
     if args.eta_min is not None:
@@ -402,20 +548,22 @@ def main():
     if args.mass_ratio is not None:
         cfg["mass_ratio"] = args.mass_ratio
         variant += f", m_i/m_e={args.mass_ratio:g}"
-    sim = Pic1D(cfg, device="cuda:0")
-    print(f"# init done: {cfg['lines'][0]}", file=sys.stderr, flush=True)
-    tune = sim.autotune(trial_steps=10)        # launch shape and sort interval (results do not depend on them)
-    print(f"# autotuned: {tune}", file=sys.stderr, flush=True)
-    launch = pick_launch(sim)
-    print(f"# launch: {launch}", file=sys.stderr, flush=True)
-    r = timed_run(sim, args.steps, args.warmup, profile=False)
-    # kernel breakdown and roofline: events around every launch, eager launches
-    rp = timed_run(sim, args.profile_steps, 0, profile=True)
-    bytes_per_launch = hbm_bytes_per_launch(rp)
-    achieved = bytes_per_launch / rp["push_avg_s"]
+    if args.init is not None:
+        cfg["lines"] = [dict(cfg["lines"][0], init=args.init, init_gamma_max=1.0e4)]
+        variant += f", {args.init} start" + (" (gamma log-uniform to 1e4)" if args.init == "hot" else "")
+    r, rp, tune, launch = plain_path(cfg, args.steps, args.warmup, args.profile_steps)
+    roof = push_roofline(rp)
     # HBM bytes per k_push launch (rocprofv3), measured on the unmodified workload only
     traffic = measured_traffic(args.backend, args.workload) if not variant else None
+    roof["traffic"] = traffic
+    roof["traffic_unit"] = "bytes/launch"
+    roof["traffic_over_algorithmic"] = traffic / roof["bytes_per_launch"] if traffic else None
     m0, m1 = r["m0"], r["m1"]
+    names = {"cfg2": "cfg2: one dipole line R_max=30, 65536 cells, 200 ppc e-/e+, atmosphere ions m_i/m_e=100, "
+                     f"pairs (curvature), {args.backend} RICS",
+             "cfg1": f"cfg1: R_max=4, 512 cells, 64 ppc, {args.backend} RICS",
+             "cfg4": f"cfg4: R_max=4, 65536 cells, 200 hot ppc e-/e+, pairs (immediate), n_max = 3 n0, "
+                     f"{args.backend} RICS"}
     res = {
         "metric": "particle-steps/s (push+RICS drag+deposit+pairs)",
         "value": r["value"],
@@ -429,18 +577,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 particles / f64 field",
         "data": "synthetic",
-        "config": {"workload": (f"{args.workload}: one dipole line R_max=30, 65536 cells, 200 ppc e-/e+, "
-                                f"atmosphere ions m_i/m_e=100, pairs (curvature), {args.backend} RICS"
-                                if args.workload == "cfg2" else f"cfg1: R_max=4, 512 cells, 64 ppc, {args.backend} RICS")
-                               + variant,
+        "config": {"workload": names[args.workload] + variant,
                    "particles_start": sum(m0["count"]), "particles_end": sum(m1["count"]),
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK,
-                     "traffic": traffic,
-                     "kernel": "k_push", "avg_ms": rp["push_avg_s"] * 1e3, "launches": rp["launches"],
-                     "bytes_per_launch": bytes_per_launch, "traffic_unit": "bytes/launch",
-                     "traffic_over_algorithmic": traffic / bytes_per_launch if traffic else None},
+                   "step_window": [m0["step"], m1["step"]], "parallelism": "single GPU"},
+        "roofline": roof,
+        "whole_step": whole_step(r, args.steps),
         "launch": launch,
         "profiled_ms_per_step": rp["ms_per_step"],
         "kernels_ms": rp["kernels_ms"],
@@ -448,13 +589,13 @@ def main():
         "counters": r["counters"],
         "gauss_residual": m1["gauss_residual"],
     }
-    sim.close()
-    del sim
     torch.cuda.empty_cache()
+    if args.workload == "cfg2" and not variant and not args.no_active:
+        res["active_phase"] = active_phase(cfg, args.steps, args.warmup, args.profile_steps)
     if not args.no_batched:
         res["batched"] = batched_path(100, 5)
     if not args.no_surrogate:
-        res["surrogate_vs_table"] = surrogate_comparison(args.surrogate_steps, 3, args.mlp_train_steps)
+        res["surrogate_vs_table"] = surrogate_comparison(args.surrogate_steps, 30, args.mlp_train_steps)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(res), flush=True)

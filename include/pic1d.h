@@ -60,6 +60,16 @@ enum { PIC1D_RICS_OFF = 0,     /* no radiation reaction                         
        PIC1D_RICS_TABLE = 2,   /* bilinear (log10 gamma, s) table of the same    */
        PIC1D_RICS_MLP = 3 };   /* the trained surrogate network (pic1d_mlp_*)    */
 
+/* The thermal photon field RICS scatters (Sec. 2.2 and Sec. 5). */
+enum { PIC1D_FIELD_RADIAL = 0,     /* photons stream radially from the star, pi/x^2 sr
+                                      (Sec. 2.2: the radial beam behind Eq. contdrag) */
+       PIC1D_FIELD_DISK = 1 };     /* the finite stellar disk (Sec. 5): the rate and
+                                      force integrated over the cone of half-angle
+                                      asin(1/x) filled by the star, at uniform
+                                      intensity, by a 24 x 24 Gauss-Legendre product
+                                      rule in (cos t, phi); TABLE backend only, the
+                                      table built on the device in float64        */
+
 /* Where a photon with E >= 2 m_e c^2 converts. */
 enum { PIC1D_CONV_IMMEDIATE = 0,   /* at the emission point (Sec. 3)              */
        PIC1D_CONV_CURVATURE = 1 }; /* where its angle to the curved line reaches
@@ -88,8 +98,13 @@ enum { PIC1D_CNT_EVENTS = 0,          /* stochastic RICS events                 
        PIC1D_CNT_ATM = 7,             /* atmosphere (e-, ion) pairs injected    */
        PIC1D_CNT_PUSHED = 8,          /* particle-steps pushed                  */
        PIC1D_CNT_DRAWS = 9,           /* Philox draws of event decisions        */
-       PIC1D_CNT_MLP_EVALS = 10,      /* surrogate-network evaluations (one per lane and call) */
+       PIC1D_CNT_MLP_EVALS = 10,      /* surrogate-network evaluations executed (one per lane
+                                         and wavefront-wide call, idle lanes included) */
        PIC1D_CNT_ANNIHILATED = 11,    /* e-/e+ pairs annihilated at the density limit */
+       PIC1D_CNT_PUSHED_IONS = 12,    /* ion steps among PIC1D_CNT_PUSHED               */
+       PIC1D_CNT_MLP_NEEDED = 13,     /* surrogate evaluations the step needs: 2 per lepton
+                                         step in the continuous regime plus its refinements,
+                                         1 in the stochastic regime                     */
        PIC1D_NCOUNTERS = 16 };
 
 typedef struct {
@@ -128,7 +143,7 @@ typedef struct {
     int32_t frozen_field;     /* 1: skip Ampere (test mode)                  */
     int32_t annihilation;     /* 1: e-/e+ pairs annihilate in cells over n_max
                                *   (Sec. 3): see pic1d_step                   */
-    int32_t pad1;
+    int32_t photon_field;     /* PIC1D_FIELD_*: where the thermal photons come from */
     double nmax_over_n0;      /* n_max/n0 per cell, all species; <= 0: d0_cells^2 */
     double atm_a0;            /* peak atmosphere density / n0; <= 0: 18 |j_twist| */
     double atm_h_cells;       /* scale height in cells; <= 0: 3 d0 / a0^(1/2) */
@@ -157,7 +172,7 @@ typedef struct {
     double energy_kinetic;    /* sum m c^2 (gamma - 1), code units            */
     double energy_field;      /* sum E^2 / 8 pi, code units                   */
     int64_t count[4];         /* live particles per species                   */
-    int64_t counters[16];     /* PIC1D_CNT_* since init (slots 12-15 reserved) */
+    int64_t counters[16];     /* PIC1D_CNT_* since init (slots 14-15 reserved) */
     int64_t step;             /* steps taken since init                       */
     int64_t avg_steps;        /* steps in the averages                        */
 } pic1d_moments_out;
@@ -192,11 +207,27 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out);
  * Errors: ECAPACITY, ENONFINITE (state frozen), ESTATE, EDEVICE. */
 int pic1d_step(pic1d_state* st, int32_t n_steps);
 
-/* Diagnostics of one line: densities, current, field, pair rate (instantaneous
- * or time-averaged since avg_start_step / the last RESET), Gauss residual
- * computed on the device in FP64 from cloud-in-cell charge, circuit potential,
- * energies, counts and counters.  flags: PIC1D_MOM_INSTANT or _AVERAGE, plus
- * PIC1D_MOM_RESET to restart the averages after reading.
+/* Diagnostics of one line (the quantities the paper's results are stated in):
+ *   - per-cell densities of each species, the plasma current and E (Sec. 4.1 and
+ *     Fig. 2: densities, multiplicity n e c / j, the field along the line), and
+ *     the pairs created per cell per step (the pair-production rate of Sec. 4.1,
+ *     Figs. 2-3), each instantaneous (the last step) or averaged over the steps
+ *     since avg_start_step or the last RESET (the paper averages over
+ *     ct/L in [5, 10]);
+ *   - the circuit potential e V_c / m_e c^2 = -(1/m_e c^2) e integral E dl
+ *     (Sec. 1, the definition of V_c; Sec. 4.1 reports it), from the cell-centred
+ *     E (one cell per unit length);
+ *   - the Gauss residual of the 1D Gauss law dE/dl = 4 pi rho (Secs. 3 and 5),
+ *     max over interior nodes of |E_{i+1/2} - E_{i-1/2} - 4 pi rho_i| / (4 pi Q ppc0),
+ *     rho from cloud-in-cell weights of the stored positions;
+ *   - the kinetic energy sum m c^2 (gamma - 1) and the field energy sum E^2 / 8 pi
+ *     (code units; the energy ledger of Sec. 3's Ampere update);
+ *   - live counts and the counters.
+ * Every sum is reproducible to the bit under any particle order: charge and
+ * kinetic energy in integer fixed point, E sums over cells in a fixed order.
+ * flags: PIC1D_MOM_INSTANT or _AVERAGE, plus PIC1D_MOM_RESET to restart the
+ * averages after reading.  out and the arrays it points to are caller-owned host
+ * memory.  Synchronises the stream.
  * Errors: EINVAL (line out of range), EDEVICE. */
 int pic1d_moments(pic1d_state* st, int32_t line, int32_t flags, pic1d_moments_out* out);
 
@@ -263,7 +294,7 @@ typedef struct {
 
 /* Autotuner of the launch shape: times trial_steps real steps (at least one
  * sort cycle) for each candidate -- push blocks per CU in {1,2,3,4,6,8}, the
- * XCD-aware tile walk on/off, sort_interval in {10,25,50,100} -- one knob at a
+ * XCD-aware tile walk on/off, sort_interval in {1,2,5,10,25,50,100} -- one knob at a
  * time, and keeps the fastest; a block count other than the starting one must
  * beat it again when the two are timed alternately twice.  The trial steps
  * advance the simulation; the
@@ -278,6 +309,55 @@ int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out);
  * Errors: EINVAL. */
 int pic1d_rics_eval(pic1d_state* st, int32_t line, int64_t n, const float* s_cells,
                     const float* u, float* F, float* ndot, float* eps);
+
+/* ---------------------------------------------------------------------------
+ * Test-particle map of the magnetosphere (Appendix A.4, Fig. 6).
+ *
+ * For each field line of equatorial radius r_eq[k] (in R*), a lepton is injected
+ * at the northern footpoint with Lorentz factor gamma0, moving away from the
+ * star, and moves under the RICS drag force of Eq. contdrag alone (radial beam,
+ * no electric field).  One device thread per line integrates
+ *   dv/dt = -beta / (R (1 + 3 v^2)^(1/2)), du/dt = F_hat, dN/dt = Ndot_hat
+ * (v = cos theta, t in units of R* over c) by fourth-order Runge-Kutta in float64 with the
+ * step limited by tol_stiff / |dF/du|, tol |u| / |F|, tol / Ndot, tol |v| / |dv/dt|
+ * and dt_max, until the particle crosses the equator or t_max L / c.
+ * Results per line (lengths in R* of arc from the northern footpoint):
+ *   gamma_min  the lowest gamma on the way to the equator (at the crossing, or
+ *              over the integration time when the drag holds the particle near
+ *              its attractor beta = mu -> 0 at the equator);
+ *   s_first    where the expected number of scatterings reaches 1 (-1: never);
+ *   s_b        where b first drops below b_pp (-1: b >= b_pp on the whole line);
+ *   l_pp       the pair-production zone, s_b - s_first, or L - 2 s_first when the
+ *              line never reaches b < b_pp (the zone then spans the equator,
+ *              taken symmetric about it), 0 without a first scattering;
+ *   crossed    1 if the particle crossed the equator.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double gamma0;            /* injection Lorentz factor (1000 in Fig. 6)   */
+    double kT_keV;            /* photon temperature (1 keV in Fig. 6)        */
+    double b_pole;            /* B* / B_QED (10)                             */
+    double b_pp;              /* pair threshold (0.1)                        */
+    double t_max;             /* integration time in units of L / c (4)      */
+    double dt_max;            /* largest step, units of R* over c (1e-2)     */
+    double tol;               /* relative change per step (1e-3)             */
+    double tol_stiff;         /* |dF/du| dt per step (0.3; RK4 is stable below 2.78) */
+    int64_t max_steps;        /* per line (1e8)                              */
+} pic1d_tp_config;
+
+typedef struct {
+    double gamma_min, s_first, s_b, l_pp, L;
+    int32_t crossed, pad;
+    int64_t steps;            /* Runge-Kutta steps taken                     */
+} pic1d_tp_result;
+
+/* Device workspace of a sweep over n lines. */
+int pic1d_testparticle_workspace_size(int32_t n, size_t* bytes);
+
+/* Sweep n >= 1 lines: r_eq (host, n values > 1), out (host, n results); the
+ * workspace (device, 256-byte aligned) holds the device copies.  Synchronises
+ * the stream.  Errors: EINVAL, ENOMEM (workspace), EDEVICE. */
+int pic1d_testparticle_sweep(const pic1d_tp_config* cfg, int32_t n, const double* r_eq, pic1d_tp_result* out,
+                             void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * RICS surrogate network (RICS backend PIC1D_RICS_MLP).
@@ -311,8 +391,13 @@ int pic1d_mlp_workspace_size(int64_t batch, int64_t n_pool, size_t* bytes);
  * first Philox block (counter (i_lo, i_hi, attempt, 7), key = seed) whose
  * inputs log10 gamma = 8 U0, s/L = U1, log10 b = -2 + 5 U2, kT = 0.3 + 0.7 U3
  * lie within the Planck cutoff y <= 80; targets in float64, stored float32.
- * x, o: device, n x 4 floats.  Synchronises the stream.  Errors: EINVAL. */
-int pic1d_mlp_samples(uint64_t seed, int64_t first, int64_t n, float* x, float* o, void* stream);
+ * x, o: device, n x 4 floats.  workspace: device, 256-byte aligned, at least
+ * PIC1D_MLP_SAMPLES_WORKSPACE bytes (the kernel's error word; the call allocates
+ * nothing).  Synchronises the stream.
+ * Errors: EINVAL, ENOMEM (workspace), ENONFINITE (a sample found no accepted draw). */
+#define PIC1D_MLP_SAMPLES_WORKSPACE 256
+int pic1d_mlp_samples(uint64_t seed, int64_t first, int64_t n, float* x, float* o, void* workspace,
+                      size_t workspace_bytes, void* stream);
 
 /* Network outputs (normalised targets, n x 3 floats, device) for raw inputs x
  * (device, n x 4) with parameters `params` (device, fp32).  Synchronises.

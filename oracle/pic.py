@@ -64,7 +64,7 @@ import math
 
 import numpy as np
 
-from . import drag, geometry, mlp, philox, rics
+from . import disk, drag, geometry, mlp, philox, rics
 
 N_SPECIES = 4
 SPECIES_SIGN = (-1.0, +1.0, -1.0, +1.0)
@@ -81,7 +81,7 @@ DEFAULTS = dict(
     table_ns=512, pairs=False, conversion="immediate", nmax_over_n0=0.0,
     atmosphere=False, atm_a0=0.0, atm_h_cells=0.0, atm_T=0.01, atm_cut=0.01,
     gravity=True, frozen_field=False, seed=0, lines=None, mlp_params=None, mlp_norm=None,
-    annihilation=True,
+    annihilation=True, photon_field="radial",
 )
 
 
@@ -127,8 +127,8 @@ class Line:
                 u = geometry.cos_of_s(self.R, sc * self.ds)
                 return (geometry.field_b(cfg['b_pole'], self.R, u), geometry.photon_mu(u),
                         geometry.radius(self.R, u))
-            self.F_tab, self.N_tab = rics.build_table(geom_at, cfg['table_nlg'], cfg['table_ns'],
-                                                      float(self.n), cfg['kT_keV'])
+            build = disk.build_table if cfg['photon_field'] == 'disk' else rics.build_table
+            self.F_tab, self.N_tab = build(geom_at, cfg['table_nlg'], cfg['table_ns'], float(self.n), cfg['kT_keV'])
 
     def geometry_at(self, xc):
         g = self.geo
@@ -140,6 +140,8 @@ class Line:
         cfg = self.cfg
         kT = cfg['kT_keV']
         mode = cfg['rics']
+        if cfg['photon_field'] == 'disk' and mode not in ('table', 'off'):
+            raise ValueError("the finite-disk photon field is tabulated (rics='table') only")
         if mode == 'exact':
             return (lambda u: rics.drag_force(u, b, mu, xr, kT),
                     lambda u: rics.drag_force_du(u, b, mu, xr, kT),

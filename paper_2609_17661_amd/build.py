@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpic1d.so")
 
-SOURCES = ["api.hip", "kernels.hip", "mlp.hip", "setup.cpp"]
+SOURCES = ["api.hip", "kernels.hip", "mlp.hip", "disk.hip", "testparticle.hip", "setup.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of the generated code

@@ -83,7 +83,8 @@ struct pic1d_state {
     unsigned long long* counters = nullptr;
     DevScalars* sc = nullptr;
     unsigned long long* rho = nullptr;
-    double* mom_out = nullptr;
+    double* mom_out = nullptr;          // [0] Gauss residual maximum; then MOM_GRID_BLOCKS pairs of partials
+    unsigned long long* mom_kin = nullptr;   // kinetic energy in fixed-point chunks
     PhotonRec* photons = nullptr;
     int32_t* n_photons = nullptr;
     float* mlp_params = nullptr;
@@ -224,7 +225,8 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->counters = cv.take<unsigned long long>((size_t)NCOUNT * CNT_REPL * L.n_lines);
     s->sc = cv.take<DevScalars>(1);
     s->rho = cv.take<unsigned long long>(L.max_nodes);
-    s->mom_out = cv.take<double>(8);
+    s->mom_out = cv.take<double>(8 + 2 * MOM_GRID_BLOCKS);
+    s->mom_kin = cv.take<unsigned long long>(4);
     s->photons = cv.take<PhotonRec>(c_pairs(L) ? (size_t)PHOTON_REPL * L.photon_region : 1);
     s->n_photons = cv.take<int32_t>(PHOTON_REPL);
     s->mlp_params = cv.take<float>(L.mlp ? MLP_NPARAM : 1);
@@ -479,6 +481,27 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     INIT_TRY(hipMemcpyAsync(st->rc_nodes, rcn.data(), rcn.size() * sizeof(double), hipMemcpyHostToDevice, s));
     if (!table.empty())
         INIT_TRY(hipMemcpyAsync(st->table, table.data(), table.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    if (cfg->rics_backend == PIC1D_RICS_TABLE && cfg->photon_field == PIC1D_FIELD_DISK) {
+        // the finite stellar disk's table, by its quadrature on the device
+        DiskTableArgs da{};
+        da.nlg = cfg->table_nlg;
+        da.ns = cfg->table_ns;
+        da.n_c = DISK_N_C;
+        da.n_phi = DISK_N_PHI;
+        gauss_legendre(DISK_N_C, da.gc, da.wc);
+        gauss_legendre(DISK_N_PHI, da.gp, da.wp);
+        da.b_pole = cfg->b_pole;
+        da.theta = cfg->kT_keV / 510.99895000;
+        for (int l = 0; l < st->lay.n_lines; ++l) {
+            const LineHost& lh = st->lines[l];
+            da.table = st->table + lh.dev.table_off;
+            da.R = cfg->lines[l].r_eq;
+            da.L = lh.L_rstar;
+            da.AF = lh.AF;
+            da.AN = lh.AN;
+            INIT_TRY(launch_disk_table(da, s));
+        }
+    }
     if (!lc.empty()) {
         INIT_TRY(hipMemcpyAsync(st->layer_cell, lc.data(), lc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         INIT_TRY(hipMemcpyAsync(st->layer_line, ll.data(), ll.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -780,7 +803,8 @@ int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out) {
     if (!rc) {
         const int s0 = st->cfg.sort_interval;
         int best_s = s0;
-        const int cand_s[] = {10, 25, 50, 100};
+        // short intervals pay where pair creation appends many unsorted particles a step
+        const int cand_s[] = {1, 2, 5, 10, 25, 50, 100};
         for (int c : cand_s) {
             if (rc || c == s0) continue;
             st->cfg.sort_interval = c;
@@ -827,21 +851,28 @@ int pic1d_moments(pic1d_state* st, int32_t line, int32_t flags, pic1d_moments_ou
     const hipStream_t s = st->stream;
     HIP_TRY(st, hipMemsetAsync(st->rho, 0, sizeof(unsigned long long) * (n + 1), s));
     HIP_TRY(st, hipMemsetAsync(st->mom_out, 0, 8 * sizeof(double), s));
+    HIP_TRY(st, hipMemsetAsync(st->mom_kin, 0, 4 * sizeof(unsigned long long), s));
     MomArgs m{};
     m.cell = st->cell[st->cur]; m.off = st->off[st->cur]; m.u = st->u[st->cur];
     m.seg_base = st->seg_base; m.n_cur = st->n_cur; m.tile_prefix = st->tile_prefix; m.nseg = st->lay.nseg;
     m.line = line; m.lines = st->dlines; m.E = st->E; m.rho = st->rho; m.out = st->mom_out;
+    m.kin = st->mom_kin; m.part = st->mom_out + 8;
     const double sign[4] = {-1.0, 1.0, -1.0, 1.0};
     for (int k = 0; k < 4; ++k) m.sign[k] = sign[k];
     m.mass_ratio = st->cfg.mass_ratio;
+    const int grid_blocks = std::max(1, std::min(MOM_GRID_BLOCKS, (n + 256) / 256));
     hipLaunchKernelGGL(k_moments_particles, dim3(st->aux_blocks), dim3(PUSH_TPB), 0, s, m);
-    hipLaunchKernelGGL(k_moments_grid, dim3(std::max(1, std::min(256, (n + 256) / 256))), dim3(256), 0, s, m);
+    hipLaunchKernelGGL(k_moments_grid, dim3(grid_blocks), dim3(256), 0, s, m);
     double mo[8];
+    std::vector<double> part(2 * (size_t)grid_blocks);
+    unsigned long long kin[4];
     DevScalars sc{};
     long long avg = 0;
     std::vector<int32_t> ncur(4);
     std::vector<unsigned long long> cnt((size_t)NCOUNT * CNT_REPL);
     HIP_TRY(st, hipMemcpyAsync(mo, st->mom_out, sizeof(mo), hipMemcpyDeviceToHost, s));
+    HIP_TRY(st, hipMemcpyAsync(part.data(), st->mom_out + 8, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(st, hipMemcpyAsync(kin, st->mom_kin, sizeof(kin), hipMemcpyDeviceToHost, s));
     HIP_TRY(st, hipMemcpyAsync(&sc, st->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
     HIP_TRY(st, hipMemcpyAsync(&avg, st->avg_count, sizeof(avg), hipMemcpyDeviceToHost, s));
     HIP_TRY(st, hipMemcpyAsync(ncur.data(), st->n_cur + 4 * line, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -878,10 +909,19 @@ int pic1d_moments(pic1d_state* st, int32_t line, int32_t flags, pic1d_moments_ou
     if (out->E) for (int c = 0; c < n; ++c) out->E[c] = E[c] / na;
     if (out->pair_rate)
         for (int c = 0; c < n; ++c) out->pair_rate[c] = average ? (double)psum[c] / na : (double)plast[c];
+    // partial sums in block order (the same bits on every call)
+    double esum = 0.0, e2 = 0.0;
+    for (int b = 0; b < grid_blocks; ++b) {
+        esum += part[2 * (size_t)b];
+        e2 += part[2 * (size_t)b + 1];
+    }
+    // kinetic energy: the three 32-bit chunk sums of sum m (gamma - 1) / m_e * 2^48
+    const unsigned __int128 ksum = (unsigned __int128)kin[0] + ((unsigned __int128)kin[1] << 32) +
+                                   ((unsigned __int128)kin[2] << 64);
     out->gauss_residual = mo[0] / (4.0 * M_PI * Q * ppc0);
-    out->v_circuit = -mo[1] / (C * C);
-    out->energy_kinetic = mo[2];
-    out->energy_field = mo[3] / (8.0 * M_PI);
+    out->v_circuit = -esum / (C * C);
+    out->energy_kinetic = (double)ksum * 0x1.0p-48 * Q * C * C;
+    out->energy_field = e2 / (8.0 * M_PI);
     for (int k = 0; k < 4; ++k) out->count[k] = 0;
     out->step = (int64_t)sc.step;
     out->avg_steps = avg;

@@ -236,10 +236,29 @@ struct MomArgs {
     const LineDev* lines;
     const double* E;
     unsigned long long* rho;   // fixed point, nodes of the line
-    double* out;               // [0] residual max, [1] sum E, [2] kinetic energy, [3] sum E^2
+    double* out;               // [0] maximum Gauss residual (bits, atomic max)
+    unsigned long long* kin;   // [3]: sum of m (gamma - 1) / m_e at 2^-48, in 32-bit chunks (exact, any order)
+    double* part;              // [MOM_GRID_BLOCKS][2]: per block sum E, sum E^2 (summed in block order on the host)
     double sign[4];
     double mass_ratio;
 };
+
+constexpr int MOM_GRID_BLOCKS = 256;          // blocks of k_moments_grid at most
+
+// Finite-disk RICS table of one line (disk.hip): Gauss-Legendre product rule of
+// n_c x n_phi nodes over the stellar disk, float64, written as float32 records.
+constexpr int DISK_MAX_NODES = 32;
+struct DiskTableArgs {
+    float4* table;              // the line's [ns][nlg] records
+    double R, b_pole, L;        // R_max / R*, B* / B_QED, line length (R*)
+    double theta, AF, AN;       // kT / m_e c^2 and the prefactors of the radial beam
+    int32_t nlg, ns, n_c, n_phi;
+    double gc[DISK_MAX_NODES], wc[DISK_MAX_NODES];   // Gauss-Legendre on [-1, 1]: cos t
+    double gp[DISK_MAX_NODES], wp[DISK_MAX_NODES];   // ... and phi
+};
+void gauss_legendre(int n, double* x, double* w);
+hipError_t launch_disk_table(const DiskTableArgs& a, hipStream_t s);
+constexpr int DISK_N_C = 24, DISK_N_PHI = 24;
 
 template <int BACKEND> __global__ void k_push(PushArgs a);
 __global__ void k_mlp_pack(const float* p, bf16x8* ft, bf16x8* bt, float* bias);

@@ -184,8 +184,9 @@ __device__ __forceinline__ float newton_midpoint(const PushArgs& a, const LineDe
 
 // One drag update over h/2 (Sec. 3): implicit midpoint where |F(p0)| tau_min <= |p0|,
 // solved by Newton from the explicit start p0 + (h/2) F(p0) -- needed only when
-// the predicted correction (h/4)|F'|(h/2)|F0| exceeds half an ulp of the result --
-// and exponential relaxation towards p_tilde = mu / (1 - mu^2)^(1/2) otherwise.
+// the predicted correction (h/4)|F'|(h/2)|F0| exceeds half an ulp of the result,
+// F' taken at p0 -- and exponential relaxation towards p_tilde = mu / (1 - mu^2)^(1/2)
+// otherwise.
 template <int BACKEND>
 __device__ __forceinline__ float drag_half(const PushArgs& a, const LineDev& L, float u0, PartGeo& g,
                                            float ptilde, bool alive, int& n_limited, int& n_newton) {
@@ -194,9 +195,8 @@ __device__ __forceinline__ float drag_half(const PushArgs& a, const LineDev& L, 
     const bool implicit = fabsf(F0) * L.tau_hat <= fabsf(u0);
     float u1 = implicit ? fmaf(0.5f * L.h, F0, u0) : fmaf(-(u0 - ptilde), L.damp, u0);
     n_limited += (alive && !implicit) ? 1 : 0;
-    // |(h/2) F0| <= |u0| h / (2 tau_min): below float32 resolution of the Newton
-    // correction whenever (h/2) |F0| itself is tiny; otherwise ask the derivative
-    if (implicit && F0 != 0.0f && 0.5f * L.h * fabsf(F0) > 0x1.0p-12f * fabsf(u0) &&
+    // F = 0 beyond the Planck cutoff (cold particles): the explicit start is the root
+    if (implicit && F0 != 0.0f &&
         0.25f * L.h * fabsf(eval_dF(L, e0)) * 0.5f * L.h * fabsf(F0) > 0x1.0p-25f * fabsf(u1)) {
         n_newton += alive ? 1 : 0;
         u1 = newton_midpoint<BACKEND>(a, L, u0, F0, u1, g);
@@ -233,7 +233,7 @@ __device__ __forceinline__ bool append_particle(const PushArgs& a, int seg, int 
 
 struct Counts {
     int events = 0, pairs = 0, escaped = 0, absorbed = 0, clipped = 0, limited = 0, newton = 0, pushed = 0,
-        draws = 0, mlp = 0;
+        draws = 0, mlp = 0, pushed_ion = 0, mlp_need = 0;
 };
 
 // Stochastic regime (b >= b_thr, Sec. 3): after the kick, a scattering event with
@@ -336,8 +336,13 @@ __device__ __forceinline__ MlpRics mlp_rics(const PushArgs& a, const bf16x8* W, 
 // |F0| tau_min > |u0|; otherwise the implicit midpoint u1 = u0 + (h/4)(F0 + F(u1)),
 // from the explicit start and refined by fixed-point iteration (contraction
 // (h/4)|F'| << 1 on this branch) where (h/2)|F0| exceeds 2^-12 |u0|, until the
-// next correction, predicted from the secant slope, is below half an ulp.  Lanes with
-// active == false return u0 but still take part in the network evaluations.
+// next correction, predicted from the secant slope, is below half an ulp.  The
+// network gives no derivative without another evaluation, so the gate is on F0
+// alone: a skipped correction is (h/4)|F'| (h/2)|F0| / (1 - (h/4)|F'|), at most
+// 2^-12 (|F'| h/4) / (1 - |F'| h/4) |u0| -- below half an ulp of u0 while
+// |F'| h/4 < 2^-13, and within the 1e-5 momentum budget while |F'| h/4 < 0.04.
+// Lanes with active == false return u0 but still take part in the network
+// evaluations.
 __device__ __forceinline__ float mlp_drag_half(const PushArgs& a, const bf16x8* W, const float* Wb, const LineDev& L,
                                                float u0, float F0, const Geo& g, float sl, float ptilde, bool active,
                                                bool alive, Counts& cnt) {
@@ -349,6 +354,7 @@ __device__ __forceinline__ float mlp_drag_half(const PushArgs& a, const bf16x8* 
 #pragma unroll 1
     for (int it = 0; it < 4; ++it) {
         if (__ballot(refine) == 0ull) break;
+        cnt.mlp_need += (refine && alive) ? 1 : 0;
         const float F1 = mlp_rics(a, W, Wb, u1, g, sl, cnt.mlp).F;
         const float un = fmaf(0.25f * L.h, F0 + F1, u0);
         // the next correction would be (h/4) F' (un - u1); F' from the secant through
@@ -444,11 +450,18 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
             const float sl = (float)(((double)c0 + (double)o0) / (double)n);
             const bool cont = g.b < L.b_thr;
             const float pt = g.mu * frsq(fmaxf(fmaf(-g.mu, g.mu, 1.0f), 1e-30f));
-            const MlpRics ra = mlp_rics(a, W, Wb, u, g, sl, cnt.mlp);
-            u = mlp_drag_half(a, W, Wb, L, u, ra.F, g, sl, pt, cont, alive, cnt);
+            // the force at u^n is needed only in the continuous regime: a wavefront with
+            // no live lane there skips the first evaluation (the step needs F at u^n and
+            // at the kicked u in that regime, Ndot at the kicked u in the stochastic one)
+            const bool any_cont = __ballot(cont && alive) != 0ull;
+            cnt.mlp_need += alive ? (cont ? 2 : 1) : 0;
+            if (any_cont) {
+                const MlpRics ra = mlp_rics(a, W, Wb, u, g, sl, cnt.mlp);
+                u = mlp_drag_half(a, W, Wb, L, u, ra.F, g, sl, pt, cont, alive, cnt);
+            }
             u += kick;
             const MlpRics rb = mlp_rics(a, W, Wb, u, g, sl, cnt.mlp);
-            u = mlp_drag_half(a, W, Wb, L, u, rb.F, g, sl, pt, cont, alive, cnt);
+            if (any_cont) u = mlp_drag_half(a, W, Wb, L, u, rb.F, g, sl, pt, cont, alive, cnt);
             if (!cont && alive) u = stochastic_step(a, L, T, line, k, c0, o0, u, g, rb.N, cnt);
         } else {
             u += kick;
@@ -513,12 +526,12 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
 }
 
 __device__ __forceinline__ void counts_flush(unsigned long long* counters, int line, Counts& c) {
-    const int v[10] = {c.events, c.pairs, c.escaped, c.absorbed, c.clipped, c.limited, c.newton, c.pushed, c.draws,
-                       c.mlp};
-    const int slot[10] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 10};
+    const int v[12] = {c.events, c.pairs, c.escaped, c.absorbed, c.clipped, c.limited, c.newton, c.pushed, c.draws,
+                       c.mlp, c.pushed_ion, c.mlp_need};
+    const int slot[12] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 13};
     const size_t rep = ((size_t)line * CNT_REPL + (blockIdx.x & (CNT_REPL - 1))) * NCOUNT;
 #pragma unroll
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < 12; ++i) {
         const int s = wave_sum_i(v[i]);
         if ((threadIdx.x & 63) == 0 && s != 0) atomicAdd(&counters[rep + slot[i]], (unsigned long long)s);
     }
@@ -780,6 +793,7 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
             advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1,
                                       o1, jm, j0, jp, d, gone, sW, sWb);
             cnt.pushed += alive ? 1 : 0;
+            cnt.pushed_ion += (alive && sp == 3) ? 1 : 0;
             jv0 += jm;
             jv1 += j0;
             jv2 += jp;
@@ -1718,15 +1732,17 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs h) {
 // Moments: cloud-in-cell charge on nodes (fixed point), kinetic energy.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_moments_particles(MomArgs m) {
-    __shared__ double sK[4];
+    __shared__ unsigned long long sK[4][3];
     // only the tiles of the requested line's four segments
     const int t_first = m.tile_prefix[4 * m.line], t_last = m.tile_prefix[4 * m.line + 4];
-    double kin = 0.0;
+    // kinetic energy sum m (gamma - 1) / m_e in fixed point: v 2^48 split exactly into
+    // three 32-bit chunks, each summed as an integer, so the total does not depend on
+    // the order in which particles are visited (bits below 2^-48 of a term dropped)
+    unsigned long long k0 = 0, k1 = 0, k2 = 0;
     for (TileWalk tw(t_last - t_first); tw.t < tw.end; tw.t += tw.stride) {
         const int t = t_first + tw.t;
         const int seg = find_segment(m.tile_prefix, m.nseg, t);
-        const int line = seg >> 2, sp = seg & 3;
-        const LineDev& L = m.lines[line];
+        const int sp = seg & 3;
         const int ncur = m.n_cur[seg];
         const int64_t base = m.seg_base[seg];
         const int i0 = (t - m.tile_prefix[seg]) * PUSH_TILE;
@@ -1743,26 +1759,46 @@ __global__ __launch_bounds__(256) void k_moments_particles(MomArgs m) {
             const double u = (double)m.u[base + i];
             atomicAdd(&m.rho[c], (unsigned long long)(sg * (4294967296ll - f)));
             atomicAdd(&m.rho[c + 1], (unsigned long long)(sg * f));
-            kin += mass * L.Q * (double)L.C * (double)L.C * (sqrt(1.0 + u * u) - 1.0);
+            // gamma - 1 = u^2 / (gamma + 1), free of cancellation at small u
+            const double v = mass * (u * u / (sqrt(fma(u, u, 1.0)) + 1.0));
+            const double sv = v * 0x1.0p48;
+            const double h2 = floor(sv * 0x1.0p-64);
+            const double r = fma(-h2, 0x1.0p64, sv);          // exact: the bits of sv below 2^64
+            const double h1 = floor(r * 0x1.0p-32);
+            const double h0 = floor(fma(-h1, 0x1.0p32, r));
+            k0 += (unsigned long long)h0;
+            k1 += (unsigned long long)h1;
+            k2 += (unsigned long long)h2;
         }
     }
-    for (int o = 32; o > 0; o >>= 1) kin += __shfl_xor(kin, o, 64);
-    if ((threadIdx.x & 63) == 0) sK[threadIdx.x >> 6] = kin;
+    for (int o = 32; o > 0; o >>= 1) {
+        k0 += __shfl_xor(k0, o, 64);
+        k1 += __shfl_xor(k1, o, 64);
+        k2 += __shfl_xor(k2, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sK[threadIdx.x >> 6][0] = k0;
+        sK[threadIdx.x >> 6][1] = k1;
+        sK[threadIdx.x >> 6][2] = k2;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double s = sK[0] + sK[1] + sK[2] + sK[3];
-        if (s != 0.0) atomicAdd(&m.out[2], s);
+    if (threadIdx.x < 3) {
+        const unsigned long long s = sK[0][threadIdx.x] + sK[1][threadIdx.x] + sK[2][threadIdx.x] + sK[3][threadIdx.x];
+        if (s != 0ull) atomicAdd(&m.kin[threadIdx.x], s);
     }
 }
 
-// Gauss residual on interior nodes, circuit potential and field energy of one line.
+// Gauss residual on interior nodes, and the per-block partial sums of E and E^2 of
+// one line (the host adds the partials in block order: the circuit potential and
+// the field energy are the same bits on every run).
 __global__ __launch_bounds__(256) void k_moments_grid(MomArgs m) {
+    __shared__ double sE[4][2];
     const LineDev& L = m.lines[m.line];
     const int n = L.n_cells;
     double rmax = 0.0, esum = 0.0, e2 = 0.0;
     const double* E = m.E + L.cell_base;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
-        if (i < n) { esum += E[i]; e2 += E[i] * E[i]; }
+        if (i < n) { esum += E[i]; e2 = fma(E[i], E[i], e2); }
         if (i >= 1 && i <= n - 1) {
             const double rho = (double)(long long)m.rho[i] * FIX_INV * L.Q;
             rmax = fmax(rmax, fabs(E[i] - E[i - 1] - 4.0 * 3.14159265358979323846 * rho));
@@ -1775,9 +1811,13 @@ __global__ __launch_bounds__(256) void k_moments_grid(MomArgs m) {
     }
     if ((threadIdx.x & 63) == 0) {
         atomicMax((unsigned long long*)&m.out[0], (unsigned long long)__double_as_longlong(rmax));
-        atomicAdd(&m.out[1], esum);
-        atomicAdd(&m.out[3], e2);
+        sE[threadIdx.x >> 6][0] = esum;
+        sE[threadIdx.x >> 6][1] = e2;
     }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        m.part[2 * blockIdx.x + threadIdx.x] =
+            ((sE[0][threadIdx.x] + sE[1][threadIdx.x]) + sE[2][threadIdx.x]) + sE[3][threadIdx.x];
 }
 
 // RICS backend evaluation at given points (diagnostics and surrogate error).

@@ -576,14 +576,34 @@ int run_grad(const MlpWork& w, TrainFwdArgs fa, hipStream_t s) {
 }
 
 double sum_loss(const MlpWork& w, int nblocks, hipStream_t s) {
-    std::vector<double> h(nblocks);
-    if (hipMemcpyAsync(h.data(), w.loss_part, sizeof(double) * nblocks, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    double h[FWD_BLOCKS];          // on the stack: the allocation-free entry point uses this too
+    nblocks = std::min(nblocks, FWD_BLOCKS);
+    if (hipMemcpyAsync(h, w.loss_part, sizeof(double) * nblocks, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return NAN;
     double t = 0.0;
-    for (double v : h) t += v;
+    for (int b = 0; b < nblocks; ++b) t += h[b];
     return t;
 }
+
+// The loss and gradient of n samples on a carved workspace w (pic1d_mlp_loss_grad
+// and its allocation-free variant).
+int loss_grad_on(const MlpWork& w, const float* params, int64_t n, const float* x, const float* t, float* grad,
+                 double* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_pack, dim3(64), dim3(MLP_TPB), 0, s, params, w.ft, w.bt, w.bias);
+    TrainFwdArgs fa{};
+    fa.ft = w.ft; fa.bias = w.bias; fa.X = reinterpret_cast<const float4*>(x); fa.T = t;
+    fa.n_batch = n; fa.n_pool = 0; fa.XN = w.XN; fa.Z = w.Z; fa.DOUT = w.DOUT;
+    fa.zlayer = w.rows * MLP_W; fa.loss_part = w.loss_part;
+    if (int rc = run_grad(w, fa, s)) return rc;
+    hipLaunchKernelGGL(k_mlp_adam, dim3(64), dim3(MLP_TPB), 0, s, w.partial, w.nchunk, nullptr, nullptr, nullptr, grad,
+                       0, adam_args(0.0, 0.0, 0.0, 1.0, 1));
+    MLP_TRY(hipGetLastError());
+    const double l = sum_loss(w, (int)std::min<int64_t>(FWD_BLOCKS, (w.rows / 16 + 3) / 4), s);
+    if (loss) *loss = l / (3.0 * (double)n);
+    return PIC1D_OK;
+}
+
 
 }  // namespace
 
@@ -597,14 +617,15 @@ int pic1d_mlp_workspace_size(int64_t batch, int64_t n_pool, size_t* bytes) {
     return PIC1D_OK;
 }
 
-int pic1d_mlp_samples(uint64_t seed, int64_t first, int64_t n, float* x, float* o, void* stream) {
+int pic1d_mlp_samples(uint64_t seed, int64_t first, int64_t n, float* x, float* o, void* workspace,
+                      size_t workspace_bytes, void* stream) {
     if (n < 0 || first < 0 || (n > 0 && (!x || !o)) || (reinterpret_cast<uintptr_t>(x) & 15) ||
         (reinterpret_cast<uintptr_t>(o) & 15))
         return fail(nullptr, PIC1D_EINVAL, "bad arguments (x, o: device, 16-byte aligned, n x 4 floats)");
+    if (int rc = check_workspace(workspace, workspace_bytes, PIC1D_MLP_SAMPLES_WORKSPACE)) return rc;
     if (n == 0) return PIC1D_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int* err = nullptr;
-    MLP_TRY(hipMalloc(reinterpret_cast<void**>(&err), sizeof(int)));
+    int* err = static_cast<int*>(workspace);
     MLP_TRY(hipMemsetAsync(err, 0, sizeof(int), s));
     uint32_t k0, k1;
     split_seed(seed, k0, k1);
@@ -615,7 +636,6 @@ int pic1d_mlp_samples(uint64_t seed, int64_t first, int64_t n, float* x, float* 
     int h = 0;
     MLP_TRY(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, s));
     MLP_TRY(hipStreamSynchronize(s));
-    MLP_TRY(hipFree(err));
     if (h) return fail(nullptr, PIC1D_ENONFINITE, "sample stream exhausted its attempts");
     return PIC1D_OK;
 }
@@ -646,19 +666,7 @@ int pic1d_mlp_loss_grad(const float* params, int64_t n, const float* x, const fl
     const MlpWork need = mlp_layout(nullptr, n, 0);
     if (int rc = check_workspace(workspace, workspace_bytes, need.bytes)) return rc;
     const MlpWork w = mlp_layout(static_cast<char*>(workspace), n, 0);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_mlp_pack, dim3(64), dim3(MLP_TPB), 0, s, params, w.ft, w.bt, w.bias);
-    TrainFwdArgs fa{};
-    fa.ft = w.ft; fa.bias = w.bias; fa.X = reinterpret_cast<const float4*>(x); fa.T = t;
-    fa.n_batch = n; fa.n_pool = 0; fa.XN = w.XN; fa.Z = w.Z; fa.DOUT = w.DOUT;
-    fa.zlayer = w.rows * MLP_W; fa.loss_part = w.loss_part;
-    if (int rc = run_grad(w, fa, s)) return rc;
-    hipLaunchKernelGGL(k_mlp_adam, dim3(64), dim3(MLP_TPB), 0, s, w.partial, w.nchunk, nullptr, nullptr, nullptr, grad,
-                       0, adam_args(0.0, 0.0, 0.0, 1.0, 1));
-    MLP_TRY(hipGetLastError());
-    const double l = sum_loss(w, (int)std::min<int64_t>(FWD_BLOCKS, (w.rows / 16 + 3) / 4), s);
-    if (loss) *loss = l / (3.0 * (double)n);
-    return PIC1D_OK;
+    return loss_grad_on(w, params, n, x, t, grad, loss, static_cast<hipStream_t>(stream));
 }
 
 int pic1d_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t t, double lr, double beta1,

@@ -90,6 +90,9 @@ const char* validate_config(const pic1d_config* c) {
     if (c->rics_backend == 2 && (int64_t)c->table_nlg * c->table_ns > (1ll << 27))
         return "table_nlg * table_ns must not exceed 2^27";
     if (c->conversion != 0 && c->conversion != 1) return "unknown conversion mode";
+    if (c->photon_field != 0 && c->photon_field != 1) return "unknown photon_field";
+    if (c->photon_field == 1 && c->rics_backend != 2 && c->rics_backend != 0)
+        return "the finite-disk photon field needs the TABLE backend";
     if (c->sort_interval < 0) return "sort_interval must be >= 0";
     int64_t cells = 0;
     for (int l = 0; l < c->n_lines; ++l) {
@@ -124,6 +127,8 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
     const double theta = c->kT_keV / kMeC2keV;
     const double base = kRe * kRstar / (4.0 * kLambdaBar * kLambdaBar);
     const double AF = base * theta * theta * theta, AN = base * theta * theta;
+    o.AF = AF;
+    o.AN = AN;
 
     LineDev& d = o.dev;
     d.cell_base = cell_base;
@@ -198,7 +203,10 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
     // RICS table for u >= 0 at log10 gamma_i = 8 i/(nlg-1), s_j = (j + 1/2) L/ns, stored as
     // [ns][nlg] records {F(i), F(i+1), Ndot(i), Ndot(i+1)} (column i+1 clamped at the end)
     o.table.clear();
-    if (c->rics_backend == 2) {
+    if (c->rics_backend == 2 && c->photon_field == 1) {
+        // the finite disk: built on the device by its quadrature (disk.hip)
+        o.table.assign(4 * (size_t)c->table_nlg * c->table_ns, 0.0f);
+    } else if (c->rics_backend == 2) {
         const int nlg = c->table_nlg, ns = c->table_ns;
         std::vector<double> Fr(nlg), Nr(nlg);
         o.table.assign(4 * (size_t)nlg * ns, 0.0f);

@@ -16,6 +16,7 @@ struct LineHost {
     LineDev dev;                       // constants uploaded to the device
     double L_rstar = 0, ds = 0;        // line length and cell length in R*
     double tau_steps = 0;
+    double AF = 0, AN = 0;             // RICS prefactors in float64
     std::vector<float> nodes;          // 4 floats per node: b, mu, x, R_curv
     std::vector<double> rc;            // R_curv per node, double
     std::vector<float> table;          // F table then Ndot table, [ns][nlg]

@@ -10,7 +10,7 @@ import os
 
 import numpy as np
 
-from .config import RICS, CONVERSION, INIT, SPECIES, complete_config
+from .config import CONVERSION, INIT, PHOTON_FIELD, RICS, SPECIES, complete_config
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpic1d.so")
 _lib = None
@@ -39,7 +39,7 @@ class CConfig(ctypes.Structure):
                 ("rics_backend", ctypes.c_int32), ("table_nlg", ctypes.c_int32), ("table_ns", ctypes.c_int32),
                 ("pairs", ctypes.c_int32), ("conversion", ctypes.c_int32), ("atmosphere", ctypes.c_int32),
                 ("gravity", ctypes.c_int32), ("frozen_field", ctypes.c_int32),
-                ("annihilation", ctypes.c_int32), ("pad1", ctypes.c_int32),
+                ("annihilation", ctypes.c_int32), ("photon_field", ctypes.c_int32),
                 ("nmax_over_n0", ctypes.c_double), ("atm_a0", ctypes.c_double), ("atm_h_cells", ctypes.c_double),
                 ("atm_T", ctypes.c_double), ("atm_cut", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("sort_interval", ctypes.c_int32), ("avg_start_step", ctypes.c_int32),
@@ -57,7 +57,8 @@ class CMoments(ctypes.Structure):
 
 
 COUNTER_NAMES = ("events", "pairs_created", "photons_escaped", "absorbed", "psc_clipped", "limited",
-                 "newton", "atm_injected", "pushed", "draws", "mlp_evals", "annihilated")
+                 "newton", "atm_injected", "pushed", "draws", "mlp_evals", "annihilated", "pushed_ions",
+                 "mlp_needed")
 
 
 class CProfile(ctypes.Structure):
@@ -86,6 +87,18 @@ class CMlpTrainResult(ctypes.Structure):
                 ("n_loss", ctypes.c_int32), ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
 
+class CTpConfig(ctypes.Structure):
+    _fields_ = [("gamma0", ctypes.c_double), ("kT_keV", ctypes.c_double), ("b_pole", ctypes.c_double),
+                ("b_pp", ctypes.c_double), ("t_max", ctypes.c_double), ("dt_max", ctypes.c_double),
+                ("tol", ctypes.c_double), ("tol_stiff", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+
+
+class CTpResult(ctypes.Structure):
+    _fields_ = [("gamma_min", ctypes.c_double), ("s_first", ctypes.c_double), ("s_b", ctypes.c_double),
+                ("l_pp", ctypes.c_double), ("L", ctypes.c_double), ("crossed", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("steps", ctypes.c_int64)]
+
+
 P = ctypes.c_void_p
 _SIGS = {
     "pic1d_workspace_size": (ctypes.c_int, [ctypes.POINTER(CConfig), ctypes.POINTER(ctypes.c_size_t)]),
@@ -105,9 +118,13 @@ _SIGS = {
     "pic1d_profile_read": (ctypes.c_int, [P, ctypes.POINTER(CProfile)]),
     "pic1d_set_graph": (ctypes.c_int, [P, ctypes.c_int32]),
     "pic1d_autotune": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(CTuneOut)]),
+    "pic1d_testparticle_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "pic1d_testparticle_sweep": (ctypes.c_int, [ctypes.POINTER(CTpConfig), ctypes.c_int32, P, P, P, ctypes.c_size_t,
+                                                P]),
     "pic1d_mlp_param_count": (ctypes.c_int, []),
     "pic1d_mlp_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
-    "pic1d_mlp_samples": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, P, P, P]),
+    "pic1d_mlp_samples": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, P, P, P, ctypes.c_size_t,
+                                         P]),
     "pic1d_mlp_forward": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]),
     "pic1d_mlp_loss_grad": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_double), P,
                                            ctypes.c_size_t, P]),
@@ -171,6 +188,7 @@ def make_cconfig(cfg):
     c.gravity = int(bool(cfg["gravity"]))
     c.frozen_field = int(bool(cfg["frozen_field"]))
     c.annihilation = int(bool(cfg["annihilation"]))
+    c.photon_field = PHOTON_FIELD[cfg["photon_field"]]
     c.seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
     c.sort_interval = int(cfg["sort_interval"])
     c.avg_start_step = int(cfg["avg_start_step"])
@@ -331,6 +349,30 @@ class Pic1D:
 
 
 # ---------------------------------------------------------------------------
+# test-particle map (Appendix A.4)
+# ---------------------------------------------------------------------------
+
+def testparticle_sweep(r_eq, gamma0=1000.0, kT_keV=1.0, b_pole=10.0, b_pp=0.1, t_max=4.0, dt_max=1e-2, tol=1e-3,
+                       tol_stiff=0.3, max_steps=100_000_000, device="cuda"):
+    """gamma_min, s_first, s_b, l_pp, L, crossed and steps of test leptons on lines r_eq
+    (one device thread per line); dict of numpy arrays."""
+    import torch
+    r = np.ascontiguousarray(r_eq, dtype=np.float64)
+    n = r.size
+    lib = load()
+    nb = ctypes.c_size_t(0)
+    _raise_global(lib.pic1d_testparticle_workspace_size(n, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=device)
+    c = CTpConfig(gamma0, kT_keV, b_pole, b_pp, t_max, dt_max, tol, tol_stiff, max_steps)
+    out = (CTpResult * n)()
+    _raise_global(lib.pic1d_testparticle_sweep(ctypes.byref(c), n, _ptr(r), ctypes.cast(out, ctypes.c_void_p),
+                                               _dev_ptr(ws), ws.numel(), _stream(ws.device)))
+    res = {k: np.array([getattr(o, k) for o in out]) for k, _ in CTpResult._fields_ if k != "pad"}
+    res["crossed"] = res["crossed"].astype(bool)
+    return res
+
+
+# ---------------------------------------------------------------------------
 # RICS surrogate network (pic1d_mlp_*): device tensors are torch float32
 # ---------------------------------------------------------------------------
 
@@ -346,6 +388,9 @@ def _dev_ptr(t):
 def _stream(device):
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+MLP_SAMPLES_WORKSPACE = 256     # bytes of device workspace of pic1d_mlp_samples (its error word)
 
 
 def mlp_param_count():
@@ -364,8 +409,9 @@ def mlp_samples(seed, first, n, device="cuda"):
     import torch
     x = torch.empty((max(n, 1), 4), dtype=torch.float32, device=device)
     o = torch.empty((max(n, 1), 4), dtype=torch.float32, device=device)
+    ws = torch.empty(MLP_SAMPLES_WORKSPACE, dtype=torch.uint8, device=x.device)
     _raise_global(load().pic1d_mlp_samples(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first), int(n), _dev_ptr(x),
-                                           _dev_ptr(o), _stream(x.device)))
+                                           _dev_ptr(o), _dev_ptr(ws), ws.numel(), _stream(x.device)))
     return x[:n], o[:n]
 
 

@@ -18,7 +18,8 @@ at the sizes of the benchmark configurations:
             the drag and the scattering events are active, pairs on up to
             n_max = 3 n0 per cell (at this resolution almost every lepton with
             gamma >~ 1e3 in the b >= 0.1 region scatters each step, and the
-            cascade is held by n_max).
+            cascade is held by n_max).  Sorted every 5 steps: pair creation
+            appends unsorted particles every step (the autotuner's choice).
 * cfg3()    the batched path: 256 lines with R_max log-uniform in [2, 100]
             (seeded draw), 1,024 to 32,768 cells per line (a power law in
             R_max through those endpoints, rounded to multiples of 256),
@@ -53,7 +54,7 @@ CFG2_STEPS = 20000
 
 CFG4 = dict(
     rics="table", table_nlg=256, table_ns=512, kT_keV=0.5, j_twist=0.5, ppc0=200.0, pairs=True,
-    conversion="immediate", nmax_over_n0=3.0, seed=0, sort_interval=20,
+    conversion="immediate", nmax_over_n0=3.0, seed=0, sort_interval=5,
     lines=[dict(r_eq=4.0, n_cells=65536, ppc_init=200, init="hot", init_gamma_max=1.0e4,
                 capacity=[40_000_000, 40_000_000, 0, 0])],
 )

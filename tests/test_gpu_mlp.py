@@ -195,7 +195,10 @@ def test_rics_eval_of_the_surrogate_matches_oracle():
 
 
 @pytest.mark.parametrize("kw", [dict(init="hot", gamma_max=3e3, pairs=True),
-                                dict(init="cold", pairs=False, ppc=24)])
+                                dict(init="cold", pairs=False, ppc=24),
+                                # tau_min = 68 steps: the implicit midpoint's fixed-point
+                                # refinement runs (Eq. implicit)
+                                dict(init="hot", gamma_max=1e4, pairs=True, eta_min=1.0, ppc=16)])
 def test_step_parity_with_the_surrogate(kw):
     from paper_2609_17661_amd import Pic1D
 
@@ -219,6 +222,10 @@ def test_step_parity_with_the_surrogate(kw):
     assert total["compared"] > 0
     assert total["excused"] <= max(3, 1e-3 * total["compared"])
     assert sim.moments(0)["gauss_residual"] <= 1e-6
+    if kw.get("eta_min", 1e3) < 10.0:
+        n_refined = sim.moments(0)["counters"]["newton"]
+        _print("  drag halves refined:", n_refined)
+        assert n_refined > 0
 
 
 # ---------------------------------------------------------------------------

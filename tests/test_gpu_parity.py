@@ -83,6 +83,17 @@ CASES = {
     # 600 e- and e+ per cell (more than the register selection holds), k = 450:
     # the radix selection over the records in memory
     "annihilation-dense-cells": workloads.small(n_cells=16, ppc=600, rics="exact", nmax_over_n0=0.5),
+    # tau_min of 679 steps on a hot R_max = 30 line: the implicit midpoint's Newton
+    # iterations run for hundreds of particles per step (Eq. implicit)
+    "exact-r30-eta10-newton": workloads.small(r_eq=30.0, n_cells=300, ppc=16, rics="exact", pairs=True,
+                                              eta_min=10.0, gamma_max=1e4),
+    "table-r30-eta10-newton": workloads.small(r_eq=30.0, n_cells=300, ppc=16, rics="table", table_nlg=256,
+                                              table_ns=300, pairs=True, eta_min=10.0, gamma_max=1e4),
+    # RICS from the finite stellar disk (Sec. 5): the table built on the device by the
+    # cone quadrature, the oracle's by its own
+    "table-disk-curvature": workloads.small(n_cells=160, ppc=12, rics="table", table_nlg=64, table_ns=96,
+                                            photon_field="disk", pairs=True, conversion="curvature",
+                                            gamma_max=1e4),
     "annihilation-table-atmosphere": workloads.small(n_cells=200, ppc=12, rics="table", table_nlg=64,
                                                      table_ns=96, pairs=True, conversion="curvature",
                                                      atmosphere=True, nmax_over_n0=1.5),
@@ -109,6 +120,10 @@ def test_step_parity(name):
         sim.step(1)   # let the state evolve between compared steps
     assert total["compared"] > 0
     assert total["excused"] <= max(3, 1e-3 * total["compared"])
+    if name.endswith("newton"):
+        n_newton = sim.moments(0)["counters"]["newton"]
+        _print("  drag halves solved by Newton:", n_newton)
+        assert n_newton > 100
 
 
 def test_cfg1_full_size_parity_and_gauss():
