@@ -412,6 +412,19 @@ int pic1d_mlp_forward(const float* params, int64_t n, const float* x, float* out
 int pic1d_mlp_loss_grad(const float* params, int64_t n, const float* x, const float* t, float* grad,
                         double* loss, void* workspace, size_t workspace_bytes, void* stream);
 
+/* pic1d_mlp_loss_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with no workspace argument.  The
+ * batch's activations and partial sums live in a static device array of 12 MiB
+ * that each GPU the library runs on holds until the process ends (its address
+ * taken once per device).  n <= 2048 samples (EINVAL beyond).  Every call on one
+ * GPU shares that array: calls that overlap on one GPU (two host threads, or
+ * two streams) race and must not be made; each call fully rewrites what it
+ * reads.  Allocates nothing; synchronises the stream when loss != NULL.
+ * Errors: EINVAL, EDEVICE. */
+int pic1d_mlp_loss_grad_static(const float* params, int64_t n, const float* x, const float* t, float* grad,
+                               double* loss, void* stream);
+
 /* One Adam step (Kingma & Ba 2015, Algorithm 1) on device arrays of
  * PIC1D_MLP_NPARAM floats; t >= 1 is the step number.  Synchronises. */
 int pic1d_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t t, double lr, double beta1,

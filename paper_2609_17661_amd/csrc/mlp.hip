@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -604,6 +605,42 @@ int loss_grad_on(const MlpWork& w, const float* params, int64_t n, const float* 
     return PIC1D_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of pic1d_mlp_loss_grad_static: the workspace of a batch of up to
+// MLP_STATIC_MAX_ROWS samples as a file-scope device array, held by each GPU the
+// library runs on until the process ends.  In host code `scratch` names a host
+// stand-in, never the device memory: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr int64_t MLP_STATIC_MAX_ROWS = 2048;
+constexpr size_t MLP_STATIC_BYTES = (size_t)12 << 20;
+constexpr int MLP_STATIC_MAX_DEVICES = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[MLP_STATIC_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[MLP_STATIC_MAX_DEVICES] = {};
+
+int static_scratch(void** out) {
+    int dev = -1;
+    MLP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MLP_STATIC_MAX_DEVICES)
+        return fail(nullptr, PIC1D_EDEVICE, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, PIC1D_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PIC1D_OK;
+}
 
 }  // namespace
 
@@ -666,6 +703,22 @@ int pic1d_mlp_loss_grad(const float* params, int64_t n, const float* x, const fl
     const MlpWork need = mlp_layout(nullptr, n, 0);
     if (int rc = check_workspace(workspace, workspace_bytes, need.bytes)) return rc;
     const MlpWork w = mlp_layout(static_cast<char*>(workspace), n, 0);
+    return loss_grad_on(w, params, n, x, t, grad, loss, static_cast<hipStream_t>(stream));
+}
+
+int pic1d_mlp_loss_grad_static(const float* params, int64_t n, const float* x, const float* t, float* grad,
+                               double* loss, void* stream) {
+    if (!params || n <= 0 || !x || !t || !grad || (reinterpret_cast<uintptr_t>(x) & 15))
+        return fail(nullptr, PIC1D_EINVAL, "bad arguments");
+    if (n > MLP_STATIC_MAX_ROWS)
+        return fail(nullptr, PIC1D_EINVAL,
+                    "n exceeds the static scratch of pic1d_mlp_loss_grad_static (at most 2048 samples per call)");
+    // every layout up to the maximum batch fits the array (checked, not assumed)
+    if (mlp_layout(nullptr, MLP_STATIC_MAX_ROWS, 0).bytes > MLP_STATIC_BYTES)
+        return fail(nullptr, PIC1D_ENOMEM, "static scratch smaller than the layout of its maximum batch");
+    void* base = nullptr;
+    if (int rc = static_scratch(&base)) return rc;
+    const MlpWork w = mlp_layout(static_cast<char*>(base), n, 0);
     return loss_grad_on(w, params, n, x, t, grad, loss, static_cast<hipStream_t>(stream));
 }
 

@@ -128,6 +128,7 @@ _SIGS = {
     "pic1d_mlp_forward": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]),
     "pic1d_mlp_loss_grad": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_double), P,
                                            ctypes.c_size_t, P]),
+    "pic1d_mlp_loss_grad_static": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_double), P]),
     "pic1d_mlp_adam": (ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, P]),
     "pic1d_mlp_train": (ctypes.c_int, [ctypes.POINTER(CMlpTrainConfig), ctypes.POINTER(CMlpTrainResult)]),
@@ -436,6 +437,19 @@ def mlp_loss_grad(params, x, t):
     _raise_global(load().pic1d_mlp_loss_grad(_dev_ptr(params.contiguous()), n, _dev_ptr(x.contiguous()),
                                              _dev_ptr(t.contiguous()), _dev_ptr(grad), ctypes.byref(loss),
                                              _dev_ptr(ws), ws.numel(), _stream(x.device)))
+    return loss.value, grad
+
+
+def mlp_loss_grad_static(params, x, t):
+    """mlp_loss_grad through the allocation-free entry point (n <= 2048); the
+    gradient tensor is the caller's."""
+    import torch
+    n = x.shape[0]
+    grad = torch.empty(mlp_param_count(), dtype=torch.float32, device=x.device)
+    loss = ctypes.c_double(0.0)
+    _raise_global(load().pic1d_mlp_loss_grad_static(_dev_ptr(params.contiguous()), n, _dev_ptr(x.contiguous()),
+                                                    _dev_ptr(t.contiguous()), _dev_ptr(grad), ctypes.byref(loss),
+                                                    _stream(x.device)))
     return loss.value, grad
 
 
