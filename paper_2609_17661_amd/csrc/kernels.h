@@ -18,7 +18,8 @@ constexpr int AUX_PPT = PUSH_TILE / PUSH_TPB;   // particles per thread when a b
 constexpr int SORT_SUB = 8;                     // sort key: cell and offset in eighths of a cell
 constexpr int SCAN_CELLS = 256;                 // cells per chunk of the sort's scan (one block)
 
-constexpr int PHOTON_REPL = 64;                 // append regions of the photon buffer
+constexpr int PHOTON_REPL = 256;                // append regions of the photon buffer (one per wavefront
+                                                // slot of a block and block mod 64: spreads the reservations)
 
 // A photon above the pair threshold, recorded by the pusher for the conversion kernel.
 struct PhotonRec {

@@ -262,7 +262,7 @@ __device__ __forceinline__ float stochastic_step(const PushArgs& a, const LineDe
         const unsigned long long m = __ballot(1);
         const int lane = threadIdx.x & 63;
         const int leader = __ffsll((long long)m) - 1;
-        const int r = blockIdx.x & (PHOTON_REPL - 1);
+        const int r = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (PHOTON_REPL - 1));
         int slot0 = 0;
         if (lane == leader) slot0 = atomicAdd(&a.n_photons[r], __popcll(m));
         const int slot = __shfl(slot0, leader, 64) + __popcll(m & ((1ull << lane) - 1ull));
@@ -855,106 +855,196 @@ template __global__ void k_push<RICS_MLP>(PushArgs);
 // is below n_max.  Float64 throughout: the member momenta are ill-conditioned in
 // eps when eps/2 is close to 1.
 // ---------------------------------------------------------------------------
-// The whole grid walks the photon records of all regions, one wavefront per 64
-// consecutive records.  Appends and counters are aggregated per wavefront and
-// line: one atomic per (wave, line) on each allocation counter and counter slot.
+// The records of all regions form one index space (regions in order); a block
+// takes CONV_CHUNK consecutive records at a time, CONV_K per thread.  The slots of
+// a chunk's pairs are reserved with one atomic per (block, line) on each
+// allocation counter: those counters are single addresses that every block
+// hits, and device-wide atomics on one address serialise.
+constexpr int CONV_K = 4;
+constexpr int CONV_CHUNK = 256 * CONV_K;
+static_assert(PHOTON_REPL % 64 == 0 && PHOTON_REPL <= 256, "region fills: PHOTON_REPL / 64 per lane of one wave");
+
+struct ConvRec {
+    int line, cell;
+    float off, up;
+    uint64_t pid;
+    bool valid, convert;
+};
+
+__device__ __forceinline__ ConvRec convert_record(const ConvertArgs& a, const int32_t* hist_in, const PhotonRec& p,
+                                                  bool valid) {
+    ConvRec c;
+    c.valid = valid;
+    c.convert = false;
+    c.line = valid ? p.line : INT32_MAX;
+    c.cell = p.cell;
+    c.off = p.off;
+    c.up = 0.0f;
+    c.pid = p.pid;
+    if (!valid) return c;
+    const LineDev& L = a.lines[p.line];
+    const int n = L.n_cells;
+    const double ud = (double)p.u_pre;
+    const double qd = sqrt(1.0 + 2.0 * (double)p.b);
+    const double eps = sqrt(1.0 + ud * ud) * (2.0 * (double)p.b) / (qd * (1.0 + qd));
+    bool ok = true;
+    if (a.conversion != 0) {
+        const double* rc = a.rc_nodes + L.node_base + p.cell;
+        const double rcx = fma((double)p.off, rc[1] - rc[0], rc[0]);
+        const double sp = (double)p.cell + (double)p.off + (double)p.dir * rcx * L.inv_ds * asin(fmin(2.0 / eps, 1.0));
+        ok = (sp >= 0.0) && (sp < (double)n);
+        c.cell = ok ? (int)floor(sp) : 0;
+        c.off = ok ? (float)(sp - (double)c.cell) : 0.0f;
+        if (c.off >= 1.0f) { c.off = 0.0f; c.cell += 1; ok = ok && c.cell < n; }
+    }
+    if (ok) {
+        const int* hc = hist_in + 4 * (size_t)(L.cell_base + c.cell);
+        c.convert = (float)(hc[0] + hc[1] + hc[2] + hc[3]) < L.nmax;
+        const double gp = 0.5 * eps;
+        c.up = p.dir * (float)sqrt(fmax((gp - 1.0) * (gp + 1.0), 0.0));
+    }
+    return c;
+}
+
+// block-wide sum and exclusive prefix (in thread order) of one int per thread
+__device__ __forceinline__ int block_scan(int v, int& total, int* s_part) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) s_part[w] = inc;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int pk = s_part[k];
+        before += (k < w) ? pk : 0;
+        total += pk;
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
 __device__ __forceinline__ void convert_photons(const ConvertArgs& a, int blk, int nblk) {
+    __shared__ int s_pref[PHOTON_REPL + 1];    // exclusive prefix of the region fills
+    __shared__ int s_part[4];
+    __shared__ int s_base[2];
     const uint64_t step = a.sc->step;
     const int32_t* hist_in = (step & 1) ? a.hist[1] : a.hist[0];
     int32_t* hist_out = (step & 1) ? a.hist[0] : a.hist[1];
     const int lane = threadIdx.x & 63;
-    const int wave = (blk * blockDim.x + threadIdx.x) >> 6;
-    const int nwave = (nblk * blockDim.x) >> 6;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    // region fills, one per lane (PHOTON_REPL == 64), read once per wavefront
-    static_assert(PHOTON_REPL == 64, "one photon region per lane");
-    const int np_lane = min(a.n_photons[lane], a.photon_region);
-    if (__ballot(np_lane > 0) == 0ull) return;
-    for (int r = 0; r < PHOTON_REPL; ++r) {
-        const int np = __shfl(np_lane, r, 64);
-        for (int i0 = wave * 64; i0 < np; i0 += nwave * 64) {
-            const int i = i0 + lane;
-            const bool valid = i < np;
+    constexpr int RPL = PHOTON_REPL / 64;      // regions per lane
+    if (threadIdx.x < 64) {
+        int f[RPL], sum = 0;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            f[k] = min(a.n_photons[lane * RPL + k], a.photon_region);
+            sum += f[k];
+        }
+        int inc = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        int run = inc - sum;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            s_pref[lane * RPL + k] = run;
+            run += f[k];
+        }
+        if (lane == 63) s_pref[PHOTON_REPL] = inc;
+    }
+    __syncthreads();
+    const int total = s_pref[PHOTON_REPL];
+    for (int c0 = blk * CONV_CHUNK; c0 < total; c0 += nblk * CONV_CHUNK) {
+        ConvRec rec[CONV_K];
+#pragma unroll
+        for (int k = 0; k < CONV_K; ++k) {
+            const int g = c0 + k * 256 + (int)threadIdx.x;
+            const bool valid = g < total;
             PhotonRec p{};
-            if (valid) p = a.photons[(size_t)r * a.photon_region + i];
-            int cs = p.cell;
-            float os = p.off;
-            bool convert = false;
-            float up = 0.0f;
             if (valid) {
-                const LineDev& L = a.lines[p.line];
-                const int n = L.n_cells;
-                const double ud = (double)p.u_pre;
-                const double qd = sqrt(1.0 + 2.0 * (double)p.b);
-                const double eps = sqrt(1.0 + ud * ud) * (2.0 * (double)p.b) / (qd * (1.0 + qd));
-                bool ok = true;
-                if (a.conversion != 0) {
-                    const double* rc = a.rc_nodes + L.node_base + p.cell;
-                    const double rcx = fma((double)p.off, rc[1] - rc[0], rc[0]);
-                    const double sp = (double)p.cell + (double)p.off +
-                                      (double)p.dir * rcx * L.inv_ds * asin(fmin(2.0 / eps, 1.0));
-                    ok = (sp >= 0.0) && (sp < (double)n);
-                    cs = ok ? (int)floor(sp) : 0;
-                    os = ok ? (float)(sp - (double)cs) : 0.0f;
-                    if (os >= 1.0f) { os = 0.0f; cs += 1; ok = ok && cs < n; }
+                int lo = 0, hi = PHOTON_REPL;          // s_pref[lo] <= g < s_pref[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pref[mid] <= g) lo = mid; else hi = mid;
                 }
-                if (ok) {
-                    const int* hc = hist_in + 4 * (size_t)(L.cell_base + cs);
-                    convert = (float)(hc[0] + hc[1] + hc[2] + hc[3]) < L.nmax;
-                    const double gp = 0.5 * eps;
-                    up = p.dir * (float)sqrt(fmax((gp - 1.0) * (gp + 1.0), 0.0));
-                }
+                p = a.photons[(size_t)lo * a.photon_region + (g - s_pref[lo])];
             }
-            // one group per line present in the wavefront
-            bool pending = valid;
-            while (true) {
-                const unsigned long long left = __ballot(pending);
-                if (left == 0ull) break;
-                const int leader = __ffsll((long long)left) - 1;
-                const int gl = __shfl(p.line, leader, 64);
-                const bool mine = pending && p.line == gl;
-                const unsigned long long mconv = __ballot(mine && convert);
-                const int nconv = __popcll(mconv);
-                int base_e = 0, base_p = 0;
-                if (lane == leader && nconv > 0) {
-                    base_e = atomicAdd(&a.alloc[4 * gl + 0], nconv);
-                    base_p = atomicAdd(&a.alloc[4 * gl + 1], nconv);
-                }
-                base_e = __shfl(base_e, leader, 64);
-                base_p = __shfl(base_p, leader, 64);
-                bool made = false;
-                if (mine && convert) {
-                    const int rank = __popcll(mconv & below);
-                    const int se = base_e + rank, spp = base_p + rank;
+            rec[k] = convert_record(a, hist_in, p, valid);
+        }
+        // one reservation per line present in the chunk, lowest line first
+        while (true) {
+            int m = INT32_MAX;
+#pragma unroll
+            for (int k = 0; k < CONV_K; ++k) m = min(m, rec[k].line);
+            m = wave_min_i(m);
+            if (lane == 0) s_part[threadIdx.x >> 6] = m;
+            __syncthreads();
+            const int gl = min(min(s_part[0], s_part[1]), min(s_part[2], s_part[3]));
+            __syncthreads();
+            if (gl == INT32_MAX) break;
+            int mine = 0, seen = 0;
+#pragma unroll
+            for (int k = 0; k < CONV_K; ++k) {
+                mine += (rec[k].line == gl && rec[k].convert) ? 1 : 0;
+                seen += (rec[k].line == gl) ? 1 : 0;
+            }
+            int nconv = 0;
+            const int before = block_scan(mine, nconv, s_part);
+            int nseen = 0;
+            block_scan(seen, nseen, s_part);
+            if (threadIdx.x == 0) {
+                s_base[0] = nconv > 0 ? atomicAdd(&a.alloc[4 * gl + 0], nconv) : 0;
+                s_base[1] = nconv > 0 ? atomicAdd(&a.alloc[4 * gl + 1], nconv) : 0;
+            }
+            __syncthreads();
+            const int base_e = s_base[0] + before, base_p = s_base[1] + before;
+            __syncthreads();
+            int made = 0, j = 0;
+#pragma unroll
+            for (int k = 0; k < CONV_K; ++k) {
+                if (rec[k].line != gl) continue;
+                if (rec[k].convert) {
+                    const int se = base_e + j, spp = base_p + j;
+                    ++j;
                     const bool e_ok = se < a.seg_cap[4 * gl + 0], p_ok = spp < a.seg_cap[4 * gl + 1];
                     if (!e_ok || !p_ok) set_error(&a.sc->err, -3);
-                    const uint4 wc = philox4x32_10(make_uint4((uint32_t)step, (uint32_t)p.pid,
-                                                              (uint32_t)(p.pid >> 32), STREAM_CHILD), a.key0, a.key1);
+                    const uint4 wc = philox4x32_10(make_uint4((uint32_t)step, (uint32_t)rec[k].pid,
+                                                              (uint32_t)(rec[k].pid >> 32), STREAM_CHILD),
+                                                   a.key0, a.key1);
                     if (e_ok) {
-                        const int64_t k = a.seg_base[4 * gl + 0] + se;
-                        a.cell[k] = cs; a.off[k] = os; a.u[k] = up; a.id[k] = id_from_words(wc.x, wc.y);
+                        const int64_t q = a.seg_base[4 * gl + 0] + se;
+                        a.cell[q] = rec[k].cell; a.off[q] = rec[k].off; a.u[q] = rec[k].up;
+                        a.id[q] = id_from_words(wc.x, wc.y);
                     }
                     if (p_ok) {
-                        const int64_t k = a.seg_base[4 * gl + 1] + spp;
-                        a.cell[k] = cs; a.off[k] = os; a.u[k] = up; a.id[k] = id_from_words(wc.z, wc.w);
+                        const int64_t q = a.seg_base[4 * gl + 1] + spp;
+                        a.cell[q] = rec[k].cell; a.off[q] = rec[k].off; a.u[q] = rec[k].up;
+                        a.id[q] = id_from_words(wc.z, wc.w);
                     }
                     if (e_ok && p_ok) {
                         const LineDev& L = a.lines[gl];
-                        int* ho = hist_out + 4 * (size_t)(L.cell_base + cs);
+                        int* ho = hist_out + 4 * (size_t)(L.cell_base + rec[k].cell);
                         atomicAdd(&ho[0], 1);
                         atomicAdd(&ho[1], 1);
-                        atomicAdd(&a.pair_step[L.cell_base + cs], 1);
-                        made = true;
+                        atomicAdd(&a.pair_step[L.cell_base + rec[k].cell], 1);
+                        ++made;
                     }
                 }
-                const int n_made = __popcll(__ballot(mine && made));
-                const int n_esc = __popcll(__ballot(mine && !made));
-                if (lane == leader) {
-                    const size_t rep = ((size_t)gl * CNT_REPL + (wave & (CNT_REPL - 1))) * NCOUNT;
-                    if (n_made) atomicAdd(&a.counters[rep + 1], (unsigned long long)n_made);
-                    if (n_esc) atomicAdd(&a.counters[rep + 2], (unsigned long long)n_esc);
-                }
-                pending = pending && !mine;
+                rec[k].line = INT32_MAX;      // done with this record
+            }
+            int n_made = 0;
+            block_scan(made, n_made, s_part);
+            if (threadIdx.x == 0) {
+                const size_t rep = ((size_t)gl * CNT_REPL + (blk & (CNT_REPL - 1))) * NCOUNT;
+                if (n_made) atomicAdd(&a.counters[rep + 1], (unsigned long long)n_made);
+                if (nseen - n_made) atomicAdd(&a.counters[rep + 2], (unsigned long long)(nseen - n_made));
             }
         }
     }
