@@ -32,7 +32,10 @@ judged against the library's EXACT backend at the workload's particles.
 Cascade run (`--cascade`, not part of the default line): 64 lines of 32,768
 cells whose hot pair seed cascades up to n_max (about 4e8 particles), stepped
 from 100-step graphs in chunks; wall time, particle count and pair multiplicity
-per chunk, and k_push's HBM rate at the final count.
+per chunk, and k_push's HBM rate at the final count.  The RICS source is the
+surrogate network (trained first on the GPU) with each line's table as its
+fallback where the network's error estimate on the line exceeds 1e-3; the
+line count on each source is reported.
 
 Inputs are synthetic (Philox initial plasma) and resident in HBM before each
 timed region.  One JSON line is printed.
@@ -396,22 +399,41 @@ def batched_path(steps, warmup):
     return out
 
 
-def cascade_run(chunks, chunk_steps, profile_steps):
+def cascade_run(chunks, chunk_steps, profile_steps, mlp_train_steps=0, fallback_tol=1e-3):
     """The combined cascade run (cfg5): 64 lines of 32,768 cells whose hot pair seed
     cascades up to n_max, stepped in chunks replayed from graphs; wall time, particle
     count and pair multiplicity per chunk, then a profiled window for k_push's HBM
-    rate at the final particle count."""
+    rate at the final particle count.  With mlp_train_steps > 0 the RICS source is
+    the surrogate network, trained on the GPU first, with each line's table as its
+    fallback where the network's error estimate on the line exceeds fallback_tol."""
+    import numpy as np
     import torch
 
-    from paper_2609_17661_amd import Pic1D, workloads
+    from paper_2609_17661_amd import Pic1D, pic1d, workloads
 
     def live(sim):
         return sum(sum(sim.moments(li)["count"]) for li in range(sim.n_lines))
 
-    t0 = time.perf_counter()
     cfg = workloads.cfg5()
+    training = None
+    if mlp_train_steps > 0:
+        tr = pic1d.mlp_train(seed=0, n_samples=1 << 22, batch=8192, steps=mlp_train_steps, lr=2e-3,
+                             lr_final=2e-6, n_loss=10)
+        training = {"steps": mlp_train_steps, "seconds": tr["seconds"], "loss_last": tr["loss_last"]}
+        print(f"# cascade surrogate trained: {training}", file=sys.stderr, flush=True)
+        cfg.update(rics="mlp", mlp_params=tr["params"], mlp_norm=tr["norm"], mlp_fallback_tol=fallback_tol)
+    t0 = time.perf_counter()
     sim = Pic1D(cfg, device="cuda:0")
     t_init = time.perf_counter() - t0
+    rics_src = {"backend": cfg["rics"]}
+    if training:
+        info = [sim.rics_line_info(li) for li in range(sim.n_lines)]
+        est = np.array([e for e, _ in info])
+        rics_src.update(training=training, fallback_tol=fallback_tol,
+                        lines_on_table=int(sum(t for _, t in info)), lines_on_network=int(sum(not t for _, t in info)),
+                        estimate_min=float(est.min()), estimate_median=float(np.median(est)),
+                        estimate_max=float(est.max()))
+        print(f"# cascade RICS source: {rics_src}", file=sys.stderr, flush=True)
     seed_pairs = sum(l["ppc_init"] * l["n_cells"] for l in cfg["lines"])
     n_start = live(sim)
     sim.set_graph(100)          # the seed evolves fastest at first: no launch trials before it
@@ -428,10 +450,12 @@ def cascade_run(chunks, chunk_steps, profile_steps):
     rp = timed_run(sim, profile_steps, 0, profile=True)
     bytes_per_launch = hbm_bytes_per_launch(rp)
     gauss = max(sim.moments(li)["gauss_residual"] for li in range(sim.n_lines))
+    src = ("surrogate network with per-line table fallback" if training else "TABLE") + " RICS"
     out = {"workload": f"cfg5: {sim.n_lines} lines, R_max log-uniform in [10, 100], 32768 cells each, hot pair "
-                       f"seed {cfg['lines'][0]['ppc_init']} e-/e+ per cell (gamma to 1e4), n_max = 6 n0 (n0 = 32), atmosphere with ions at "
-                       f"m_i/m_e = 100, pairs (curvature), pair annihilation over n_max, TABLE RICS, 100-step graphs",
-           "init_seconds": t_init, "wall_seconds": wall, "steps": chunks * chunk_steps,
+                       f"seed {cfg['lines'][0]['ppc_init']} e-/e+ per cell (gamma to 1e4), "
+                       f"n_max = {cfg['nmax_over_n0']:g} n0 (n0 = {cfg['ppc0']:g}), atmosphere with ions at "
+                       f"m_i/m_e = 100, pairs (curvature), pair annihilation over n_max, {src}, 100-step graphs",
+           "rics": rics_src, "init_seconds": t_init, "wall_seconds": wall, "steps": chunks * chunk_steps,
            "particles_start": n_start, "particles_end": rows[-1]["particles"],
            "pair_multiplicity": pairs / seed_pairs, "pairs_annihilated": annihilated, "chunks": rows,
            "kernels_ms_at_end": rp["kernels_ms"],
@@ -519,6 +543,8 @@ def main():
     ap.add_argument("--cascade", action="store_true",
                     help="only the combined cascade run (cfg5), as its own JSON line")
     ap.add_argument("--cascade-chunks", type=int, default=6)
+    ap.add_argument("--cascade-mlp-train-steps", type=int, default=20000,
+                    help="training steps of the cascade run's surrogate (0: the table alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures the hot path on one GPU only (requested --gpus {args.gpus}); "
@@ -533,7 +559,8 @@ def main():
     from paper_2609_17661_amd import Pic1D, workloads
 
     if args.cascade:
-        print(json.dumps({"cascade": cascade_run(args.cascade_chunks, 100, 20)}), flush=True)
+        print(json.dumps({"cascade": cascade_run(args.cascade_chunks, 100, 20, args.cascade_mlp_train_steps)}),
+              flush=True)
         return
     if args.surrogate_only:
         print(json.dumps({"surrogate_vs_table": surrogate_comparison(args.surrogate_steps, 30, args.mlp_train_steps)}),

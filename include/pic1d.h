@@ -154,6 +154,15 @@ typedef struct {
     int32_t avg_start_step;   /* accumulate averages from this step; < 0 off */
     const float* mlp_weights; /* MLP backend: host, pic1d_mlp_param_count() fp32 parameters */
     const float* mlp_norm;    /* MLP backend: host, 6 floats: output mean[3], std[3] */
+    double mlp_fallback_tol;  /* MLP backend: > 0 gives every line a RICS table and an error
+                               *   estimate of the network on it -- the largest relative
+                               *   error of F_hat and Ndot_hat against the closed forms
+                               *   over the table's nodes (where they are significant:
+                               *   |F| h >= 1e-9 max(u, 1), Ndot h >= 1e-9), evaluated on the
+                               *   device at init -- and lines whose estimate exceeds the
+                               *   tolerance use their table instead of the network;
+                               *   any R_max and field range are then accepted.
+                               *   0: the network everywhere (R_max = 4 lines only). */
     void* workspace;          /* device, >= pic1d_workspace_size bytes, 256-B aligned */
     size_t workspace_bytes;
     void* stream;             /* hipStream_t all work is enqueued on          */
@@ -301,6 +310,12 @@ typedef struct {
  * physics does not depend on these choices (particle order and launch shape do
  * not change any result).  Errors: EINVAL, ESTATE, ECAPACITY, ENONFINITE. */
 int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out);
+
+/* The surrogate's error estimate on one line and whether the line uses its
+ * table instead (MLP backend with mlp_fallback_tol > 0; otherwise *error = -1 and
+ * *uses_table = 1 for the TABLE backend, 0 for the others).  Host outputs.
+ * Errors: EINVAL. */
+int pic1d_rics_line_info(pic1d_state* st, int32_t line, double* error, int32_t* uses_table);
 
 /* Evaluate the configured RICS backend of one line at n points, exactly as
  * the pusher does (float32): device arrays s_cells[n] (arc length in cells,

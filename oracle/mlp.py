@@ -305,6 +305,42 @@ def surrogate_force_du(params, norm, u, s_over_L_eff, b, mu, x, kT):
     return np.where(y <= rics.Y_CUTOFF, dFa, 0.0)
 
 
+def line_error_estimate(params, norm, b, mu, x, n_lg, kT, h, surrogate=None):
+    """Largest relative error of the surrogate against the definitions on one line's table nodes.
+
+    The nodes are those of the line's RICS table (log10 gamma_i = 8 i/(n_lg - 1),
+    rows at arc-length fractions (j + 1/2)/n_s with geometry (b, mu, x)[j]), u >= 0;
+    the definitions are Eqs. contdrag and scatteringNdot.  A node counts for the
+    force where the exact force moves u by at least 1e-9 max(u, 1) in one step of
+    length h (R*/c), for the rate where it gives at least 1e-9 scatterings a step.  A
+    non-finite network output counts as an infinite error.  surrogate(u, s/L, b,
+    mu, x, kT) -> (F_hat, Ndot_hat) replaces the network (for the pins).
+    """
+    if surrogate is None:
+        def surrogate(u, sl, bj, muj, xj, kT_):
+            F, N, _ = surrogate_rics(params, norm, u, sl, bj, muj, xj, kT_)
+            return F, N
+    b, mu, x = (np.asarray(a, dtype=np.float64) for a in (b, mu, x))
+    n_s = b.shape[0]
+    gam = 10.0 ** (8.0 * np.arange(n_lg, dtype=np.float64) / (n_lg - 1))
+    u = np.sqrt(np.maximum(gam * gam - 1.0, 0.0))
+    worst = 0.0
+    for j in range(n_s):
+        F, N = surrogate(u, (j + 0.5) / n_s, b[j], mu[j], x[j], kT)
+        Fe = rics.drag_force(u, b[j], mu[j], x[j], kT)
+        Ne = rics.scatter_rate(u, b[j], mu[j], x[j], kT)
+        sf = (np.abs(Fe) * h >= 1e-9 * np.maximum(u, 1.0)) & (Fe != 0.0)
+        sn = Ne * h >= 1e-9
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+            ef = np.abs(F[sf] - Fe[sf]) / np.abs(Fe[sf])
+            en = np.abs(N[sn] - Ne[sn]) / Ne[sn]
+        e = np.concatenate([ef, en])
+        if e.size:
+            e = np.where(np.isfinite(e), e, np.inf)
+            worst = max(worst, float(e.max()))
+    return worst
+
+
 def normalisation(O):
     """Per-output mean and standard deviation of a sample set (the normalisation of the targets)."""
     O = np.asarray(O, dtype=np.float64)

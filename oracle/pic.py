@@ -80,7 +80,7 @@ DEFAULTS = dict(
     eta_min=1.0e3, b_thr=0.1, mass_ratio=100.0, rics="table", table_nlg=256,
     table_ns=512, pairs=False, conversion="immediate", nmax_over_n0=0.0,
     atmosphere=False, atm_a0=0.0, atm_h_cells=0.0, atm_T=0.01, atm_cut=0.01,
-    gravity=True, frozen_field=False, seed=0, lines=None, mlp_params=None, mlp_norm=None,
+    gravity=True, frozen_field=False, seed=0, lines=None, mlp_params=None, mlp_norm=None, mlp_fallback_tol=0.0,
     annihilation=True, photon_field="radial",
 )
 
@@ -122,13 +122,26 @@ class Line:
         prof = a0 * np.exp(-d / hat)
         self.atm_target = np.where(prof >= cfg['atm_cut'],
                                    np.floor(prof * cfg['ppc0']), 0.0).astype(np.int64)
-        if cfg['rics'] == 'table':
+        # the surrogate's error estimate on this line and, above the tolerance, the
+        # table as its source (mlp_fallback_tol > 0)
+        fallback = cfg['rics'] == 'mlp' and cfg['mlp_fallback_tol'] > 0.0
+        self.mlp_error = None
+        self.use_table = cfg['rics'] == 'table'
+        if cfg['rics'] == 'table' or fallback:
             def geom_at(sc):
                 u = geometry.cos_of_s(self.R, sc * self.ds)
                 return (geometry.field_b(cfg['b_pole'], self.R, u), geometry.photon_mu(u),
                         geometry.radius(self.R, u))
             build = disk.build_table if cfg['photon_field'] == 'disk' else rics.build_table
             self.F_tab, self.N_tab = build(geom_at, cfg['table_nlg'], cfg['table_ns'], float(self.n), cfg['kT_keV'])
+        if fallback:
+            _, s_rows = rics.table_axes(cfg['table_nlg'], cfg['table_ns'], float(self.n))
+            b_r, mu_r, x_r = geom_at(s_rows)
+            nm = np.asarray(cfg['mlp_norm'], dtype=np.float64).reshape(2, 3)
+            self.mlp_error = mlp.line_error_estimate(np.asarray(cfg['mlp_params'], dtype=np.float64),
+                                                     (nm[0], nm[1]), b_r, mu_r, x_r, cfg['table_nlg'],
+                                                     cfg['kT_keV'], self.h)
+            self.use_table = self.mlp_error > cfg['mlp_fallback_tol']
 
     def geometry_at(self, xc):
         g = self.geo
@@ -146,7 +159,7 @@ class Line:
             return (lambda u: rics.drag_force(u, b, mu, xr, kT),
                     lambda u: rics.drag_force_du(u, b, mu, xr, kT),
                     lambda u: rics.scatter_rate(u, b, mu, xr, kT))
-        if mode == 'table':
+        if mode == 'table' or (mode == 'mlp' and self.use_table):
             L = float(self.n)
             return (lambda u: rics.table_lookup(self.F_tab, self.N_tab, u, xc, L)[0],
                     lambda u: rics.table_lookup(self.F_tab, self.N_tab, u, xc, L)[2],
@@ -187,6 +200,9 @@ class State:
         self.lines = []
         base = 0
         for i, lc in enumerate(cfg['lines']):
+            # a line taken out of a batch keeps its global cell numbering (the
+            # atmosphere's draws are keyed by global cell) through 'cell_base'
+            base = int(lc.get('cell_base', base))
             self.lines.append(Line(cfg, i, lc, base))
             base += int(lc['n_cells'])
         self.step = 0

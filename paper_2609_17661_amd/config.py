@@ -43,6 +43,7 @@ DEFAULTS = dict(
     lines=None,
     mlp_params=None,    # RICS "mlp": the network's 50,563 parameters (float32 values)
     mlp_norm=None,      # RICS "mlp": output mean[3] and std[3]
+    mlp_fallback_tol=0.0,   # RICS "mlp": > 0, lines where the network's error estimate exceeds it use a table
 )
 
 

@@ -1,6 +1,8 @@
 // C ABI of the pic1d library (include/pic1d.h): state, workspace carving,
 // kernel launches.
 #include <hip/hip_runtime.h>
+
+#include <cstring>
 #include <math.h>
 #include <string.h>
 
@@ -42,6 +44,8 @@ struct Layout {
     int32_t photon_region = 0;   // photon records per append region
     int32_t n_chunks = 0;        // chunks of SCAN_CELLS cells over all lines (the sort's scan)
     bool mlp = false;            // surrogate-network RICS backend
+    bool mlp_fallback = false;   // ... with the table of every line as its fallback
+    int32_t table_ns = 0;
 };
 
 }  // namespace
@@ -92,6 +96,9 @@ struct pic1d_state {
     bf16x8* mlp_bt = nullptr;
     float* mlp_bias = nullptr;
     float mlp_norm[6] = {0, 0, 0, 1, 1, 1};
+    double* row_geo = nullptr;                 // MLP with table fallback: (b, mu, x) per table row
+    unsigned int* mlp_err_bits = nullptr;      // ... the network's error estimate per line (float bits)
+    std::vector<double> mlp_error;             // ... and on the host
     // per-kernel event timing (pic1d_profile)
     int prof_on = 0;
     // launch shape (tunable) and captured step graphs
@@ -174,6 +181,8 @@ Layout plan_layout(const pic1d_config* c, std::vector<LineHost>* lines_out) {
                                                  (1ll << 30) / PHOTON_REPL);
     L.table_floats = toff;
     L.mlp = c->rics_backend == PIC1D_RICS_MLP;
+    L.mlp_fallback = L.mlp && c->mlp_fallback_tol > 0.0;
+    L.table_ns = c->table_ns;
     return L;
 }
 
@@ -233,6 +242,8 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->mlp_ft = cv.take<bf16x8>(L.mlp ? FT_TOTAL * 64 : 1);
     s->mlp_bt = cv.take<bf16x8>(L.mlp ? BT_TOTAL * 64 : 1);
     s->mlp_bias = cv.take<float>(L.mlp ? MLP_BIAS : 1);
+    s->row_geo = cv.take<double>(L.mlp_fallback ? 3 * (size_t)L.n_lines * L.table_ns : 1);
+    s->mlp_err_bits = cv.take<unsigned int>(L.mlp_fallback ? L.n_lines : 1);
 }
 
 PushArgs push_args(pic1d_state* st) {
@@ -386,9 +397,10 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     *out = nullptr;
     const char* why = validate_config(cfg);
     if (why[0]) return fail(nullptr, PIC1D_EINVAL, why);
+    const bool mlp_fallback = cfg->rics_backend == PIC1D_RICS_MLP && cfg->mlp_fallback_tol > 0.0;
     if (cfg->rics_backend == PIC1D_RICS_MLP) {
         if (!cfg->mlp_weights || !cfg->mlp_norm) return fail(nullptr, PIC1D_EINVAL, "MLP backend needs mlp_weights and mlp_norm");
-        for (int l = 0; l < cfg->n_lines; ++l)
+        for (int l = 0; l < cfg->n_lines && !mlp_fallback; ++l)
             if (cfg->lines[l].r_eq != 4.0)
                 return fail(nullptr, PIC1D_EINVAL, "the surrogate network covers the R_max = 4 line only");
         if (!(cfg->kT_keV >= 0.3 && cfg->kT_keV <= 1.0))
@@ -513,7 +525,7 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
                             hipMemcpyHostToDevice, s));
     if (st->lay.mlp) {
         for (int k = 0; k < 6; ++k) st->mlp_norm[k] = cfg->mlp_norm[k];
-        for (int l = 0; l < st->lay.n_lines; ++l) {
+        for (int l = 0; l < st->lay.n_lines && !mlp_fallback; ++l) {
             const std::vector<float>& nd = st->lines[l].nodes;      // {b, mu, x, 0} per node
             for (size_t i = 0; i < nd.size(); i += 4)
                 if (!(nd[i] >= 0.01f && nd[i] <= 1000.0f))
@@ -522,6 +534,30 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
         INIT_TRY(hipMemcpyAsync(st->mlp_params, cfg->mlp_weights, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_mlp_pack, dim3(64), dim3(256), 0, s, st->mlp_params, st->mlp_ft, st->mlp_bt, st->mlp_bias);
         INIT_TRY(hipGetLastError());
+        st->mlp_error.assign(st->lay.n_lines, 0.0);
+        if (mlp_fallback) {
+            // the network's error estimate on every line, then each line's source
+            std::vector<double> rg;
+            for (int l = 0; l < st->lay.n_lines; ++l)
+                rg.insert(rg.end(), st->lines[l].row_geo.begin(), st->lines[l].row_geo.end());
+            INIT_TRY(hipMemcpyAsync(st->row_geo, rg.data(), rg.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            INIT_TRY(hipMemsetAsync(st->mlp_err_bits, 0, st->lay.n_lines * sizeof(unsigned int), s));
+            hipLaunchKernelGGL(k_mlp_line_error, dim3(std::max(1, st->n_cu)), dim3(256), 0, s, push_args(st),
+                               st->row_geo, cfg->kT_keV, st->mlp_err_bits);
+            INIT_TRY(hipGetLastError());
+            std::vector<unsigned int> bits(st->lay.n_lines);
+            INIT_TRY(hipMemcpyAsync(bits.data(), st->mlp_err_bits, bits.size() * sizeof(unsigned int),
+                                    hipMemcpyDeviceToHost, s));
+            INIT_TRY(hipStreamSynchronize(s));
+            for (int l = 0; l < st->lay.n_lines; ++l) {
+                float e;
+                std::memcpy(&e, &bits[l], sizeof(float));
+                st->mlp_error[l] = e;
+                ld[l].use_table = (double)e > cfg->mlp_fallback_tol ? 1 : 0;
+                st->lines[l].dev.use_table = ld[l].use_table;
+            }
+            INIT_TRY(hipMemcpyAsync(st->dlines, ld.data(), ld.size() * sizeof(LineDev), hipMemcpyHostToDevice, s));
+        }
     }
 
     // initial pair plasma
@@ -1050,6 +1086,13 @@ int pic1d_set_step(pic1d_state* st, int64_t step) {
     sc.step = (uint64_t)step;
     HIP_TRY(st, copy_sync(st->stream, st->sc, &sc, sizeof(sc), hipMemcpyHostToDevice));
     st->host_step = (uint64_t)step;
+    return PIC1D_OK;
+}
+
+int pic1d_rics_line_info(pic1d_state* st, int32_t line, double* error, int32_t* uses_table) {
+    if (!st || !error || !uses_table || line < 0 || line >= st->lay.n_lines) return fail(st, PIC1D_EINVAL, "bad arguments");
+    *error = (st->lay.mlp_fallback && line < (int)st->mlp_error.size()) ? st->mlp_error[line] : -1.0;
+    *uses_table = st->lines[line].dev.use_table;
     return PIC1D_OK;
 }
 

@@ -263,6 +263,11 @@ constexpr int DISK_N_C = 24, DISK_N_PHI = 24;
 
 template <int BACKEND> __global__ void k_push(PushArgs a);
 __global__ void k_mlp_pack(const float* p, bf16x8* ft, bf16x8* bt, float* bias);
+// The surrogate's error estimate on every line: the largest relative error of
+// F_hat and Ndot_hat against the float64 closed forms over the line's table nodes,
+// as float bits in err[line] (0 before the launch).  row_geo: per line, per table
+// row, (b, mu, x) at the row centre.
+__global__ void k_mlp_line_error(PushArgs a, const double* row_geo, double kT_keV, unsigned int* err);
 __global__ void k_rics_eval_mlp(PushArgs a, int line, int64_t n, const float* s_cells, const float* u, float* F,
                                 float* N, float* eps);
 __global__ void k_append(ConvertArgs ca, AtmArgs aa, int conv_blocks);

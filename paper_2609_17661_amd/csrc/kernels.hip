@@ -676,8 +676,11 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
         // the first cell's cache, loaded early so that its latency hides under the
         // tile set-up below
         const float qmC = ((sp == 0 || sp == 2) ? -1.0f : (sp == 1 ? 1.0f : a.qm_ion)) * L.invC;
+        // the surrogate's lines whose error estimate failed take their table (tile-uniform)
+        const bool tab_line = BACKEND == RICS_MLP && L.use_table != 0;
         CellCache cc;
-        cache_load<BACKEND>(cc, a, L, qmC, first);
+        if (tab_line) cache_load<RICS_TABLE>(cc, a, L, qmC, first);
+        else cache_load<BACKEND>(cc, a, L, qmC, first);
         // The order in which the lane visits its slots: by cell (dead slots last), so
         // that the run accumulator and the cell cache see each cell once however the
         // particles of a cell are ordered in memory.  A 19-comparator sorting network
@@ -782,7 +785,8 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
                     flush_run(3);
                     jv0 = jv1 = jv2 = hc = 0;
                 }
-                cache_load<BACKEND>(cc, a, L, qmC, c0);
+                if (tab_line) cache_load<RICS_TABLE>(cc, a, L, qmC, c0);
+                else cache_load<BACKEND>(cc, a, L, qmC, c0);
                 key = c0;
             }
             float uq = sPu[wid][slot][lane];
@@ -790,8 +794,17 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
             int c1, d, jm, j0, jp;
             float o1;
             bool gone;
-            advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1,
-                                      o1, jm, j0, jp, d, gone, sW, sWb);
+            if constexpr (BACKEND == RICS_MLP) {
+                if (tab_line)
+                    advance_particle<RICS_TABLE>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt,
+                                                 c1, o1, jm, j0, jp, d, gone, sW, sWb);
+                else
+                    advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1,
+                                              o1, jm, j0, jp, d, gone, sW, sWb);
+            } else {
+                advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1,
+                                          o1, jm, j0, jp, d, gone, sW, sWb);
+            }
             cnt.pushed += alive ? 1 : 0;
             cnt.pushed_ion += (alive && sp == 3) ? 1 : 0;
             jv0 += jm;
@@ -1912,8 +1925,8 @@ __global__ __launch_bounds__(256) void k_moments_grid(MomArgs m) {
 
 // RICS backend evaluation at given points (diagnostics and surrogate error).
 template <int BACKEND>
-__global__ __launch_bounds__(256) void k_rics_eval(PushArgs a, int line, int64_t n, const float* s_cells,
-                                                   const float* uin, float* F, float* N, float* eps) {
+__device__ __forceinline__ void rics_eval_point(const PushArgs& a, int line, int64_t n, const float* s_cells,
+                                                const float* uin, float* F, float* N, float* eps) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const LineDev L = a.lines[line];
@@ -1932,6 +1945,11 @@ __global__ __launch_bounds__(256) void k_rics_eval(PushArgs a, int line, int64_t
     N[i] = nd;
     eps[i] = photon_energy(fsqrt(fmaf(u, u, 1.0f)), g.b);
 }
+template <int BACKEND>
+__global__ __launch_bounds__(256) void k_rics_eval(PushArgs a, int line, int64_t n, const float* s_cells,
+                                                   const float* uin, float* F, float* N, float* eps) {
+    rics_eval_point<BACKEND>(a, line, n, s_cells, uin, F, N, eps);
+}
 template __global__ void k_rics_eval<RICS_OFF>(PushArgs, int, int64_t, const float*, const float*, float*, float*, float*);
 template __global__ void k_rics_eval<RICS_EXACT>(PushArgs, int, int64_t, const float*, const float*, float*, float*, float*);
 template __global__ void k_rics_eval<RICS_TABLE>(PushArgs, int, int64_t, const float*, const float*, float*, float*, float*);
@@ -1940,6 +1958,10 @@ template __global__ void k_rics_eval<RICS_TABLE>(PushArgs, int, int64_t, const f
 // network together, lanes past n on a dummy point).
 __global__ __launch_bounds__(256) void k_rics_eval_mlp(PushArgs a, int line, int64_t n, const float* s_cells,
                                                        const float* uin, float* F, float* N, float* eps) {
+    if (a.lines[line].use_table) {           // this line takes its table (uniform over the launch)
+        rics_eval_point<RICS_TABLE>(a, line, n, s_cells, uin, F, N, eps);
+        return;
+    }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = i < n;
     const LineDev L = a.lines[line];
@@ -1955,6 +1977,67 @@ __global__ __launch_bounds__(256) void k_rics_eval_mlp(PushArgs a, int line, int
         F[i] = rr.F;
         N[i] = rr.N;
         eps[i] = photon_energy(fsqrt(fmaf(u, u, 1.0f)), g.b);
+    }
+}
+
+// The surrogate's error estimate on each line (MLP backend with table fallback):
+// every table node (log10 gamma_i, row centre s_j) of every line is evaluated by
+// the network as the pusher evaluates it (float32 geometry, inputs at s_j / L) and
+// by the closed forms of Eqs. contdrag and scatteringNdot in float64; the line's
+// estimate is the largest relative error of F and Ndot where they are significant
+// (|F| h >= 1e-9 max(u, 1) and Ndot h >= 1e-9).  One node per lane; the whole wavefront
+// evaluates the network together.
+__global__ __launch_bounds__(256) void k_mlp_line_error(PushArgs a, const double* row_geo, double kT_keV,
+                                                        unsigned int* err) {
+    __shared__ bf16x8 sW[FT_TOTAL * 64];
+    __shared__ float sWb[MLP_BIAS];
+    for (int e = threadIdx.x; e < FT_TOTAL * 64; e += blockDim.x) sW[e] = a.mlp_ft[e];
+    for (int e = threadIdx.x; e < MLP_BIAS; e += blockDim.x) sWb[e] = a.mlp_bias[e];
+    __syncthreads();
+    const int nlg = a.nlg, ns = a.ns;
+    const int64_t per_line = (int64_t)nlg * ns;
+    const int n_lines = a.nseg >> 2;
+    const int64_t total = per_line * n_lines;
+    const double theta = kT_keV / 510.99895000;
+    const double base = 2.8179403262e-13 * 1.0e6 / (4.0 * 3.8615926796e-11 * 3.8615926796e-11);
+    const double AF = base * theta * theta * theta, AN = base * theta * theta;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane of a wavefront runs the same number of iterations (the network needs all 64)
+    const int64_t rounds = (total + stride - 1) / stride;
+    for (int64_t it = 0; it < rounds; ++it) {
+        const int64_t e = it * stride + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const bool valid = e < total;
+        const int64_t ee = valid ? e : 0;
+        const int line = (int)(ee / per_line);
+        const int rem = (int)(ee % per_line);
+        const int j = rem / nlg, i = rem % nlg;
+        const LineDev& L = a.lines[line];
+        const double* rg = row_geo + 3 * ((size_t)line * ns + j);
+        const double b = rg[0], mu = rg[1], x = rg[2];
+        const double gam = pow(10.0, 8.0 * i / (nlg - 1));
+        const double u = sqrt(fmax(gam * gam - 1.0, 0.0));
+        Geo g;
+        g.b = (float)b;
+        g.mu = (float)mu;
+        g.ix2 = frcp((float)x * (float)x);
+        g.by = g.b * L.inv_theta;
+        int dummy = 0;
+        const MlpRics r = mlp_rics(a, sW, sWb, (float)u, g, (float)((j + 0.5) / ns), dummy);
+        // closed forms (float64)
+        const double y = b / (theta * (gam - u * mu));
+        double Fe = 0.0, Ne = 0.0;
+        if (y <= 80.0) {
+            const double em1 = expm1(y);
+            Fe = AF / (x * x) * (gam * mu - u) * y * y * y / em1;
+            Ne = AN / (x * x * gam) * y * y / em1;
+        }
+        const double h = (double)L.h;
+        double worst = 0.0;
+        if (valid && fabs(Fe) * h >= 1e-9 * fmax(u, 1.0) && Fe != 0.0) worst = fabs((double)r.F - Fe) / fabs(Fe);
+        if (valid && Ne * h >= 1e-9) worst = fmax(worst, fabs((double)r.N - Ne) / Ne);
+        if (!(worst <= 3.0e38)) worst = 3.0e38;        // non-finite network output: no trust
+        const float wf = (float)worst;
+        if (valid && wf > 0.0f) atomicMax(&err[line], __float_as_uint(wf));
     }
 }
 

@@ -53,6 +53,9 @@ struct LineDev {
     float grav;           // T C / h_atm: |du| per step of a unit-mass particle in the layer
     float nmax;           // n_max per cell (all species)
     float half_n;         // n_cells / 2
+    int32_t use_table;    // 1: the line's RICS comes from its table (TABLE backend, or the
+                          //    MLP backend where the network's error estimate exceeds the tolerance)
+    int32_t pad_ut;
     float lgk;            // table: (nlg - 1)/16 log10(2): fractional column per unit log2 gamma^2
     float lgk_hi, lgk_lo; // lgk split into a 10-fraction-bit head and the rest
     float s_scale_f;      // table: s_scale in float32 (rows per cell)

@@ -75,6 +75,10 @@ double cos_theta_at(double R, double s) {
     return v;
 }
 
+bool config_has_table(const pic1d_config* c) {
+    return c->rics_backend == 2 || (c->rics_backend == 3 && c->mlp_fallback_tol > 0.0);
+}
+
 const char* validate_config(const pic1d_config* c) {
     if (!c) return "config is NULL";
     if (c->n_lines < 1 || c->n_lines > 4096 || !c->lines) return "n_lines must be in [1, 4096] with lines given";
@@ -85,9 +89,10 @@ const char* validate_config(const pic1d_config* c) {
     if (!(c->mass_ratio >= 1.0)) return "mass_ratio must be >= 1";
     if (!(c->eta_min > 0.0)) return "eta_min must be positive";
     if (c->rics_backend < 0 || c->rics_backend > 3) return "unknown rics_backend";
-    if (c->rics_backend == 2 && (c->table_nlg < 2 || c->table_ns < 2 || c->table_nlg > 4096 || c->table_ns > 65536))
+    if (!(c->mlp_fallback_tol >= 0.0)) return "mlp_fallback_tol must be >= 0";
+    if (config_has_table(c) && (c->table_nlg < 2 || c->table_ns < 2 || c->table_nlg > 4096 || c->table_ns > 65536))
         return "table dimensions out of range";
-    if (c->rics_backend == 2 && (int64_t)c->table_nlg * c->table_ns > (1ll << 27))
+    if (config_has_table(c) && (int64_t)c->table_nlg * c->table_ns > (1ll << 27))
         return "table_nlg * table_ns must not exceed 2^27";
     if (c->conversion != 0 && c->conversion != 1) return "unknown conversion mode";
     if (c->photon_field != 0 && c->photon_field != 1) return "unknown photon_field";
@@ -144,8 +149,10 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
     d.A_N = (float)AN;
     d.inv_theta = (float)(1.0 / theta);
     d.b_thr = (float)c->b_thr;
-    d.s_scale = c->rics_backend == 2 ? (double)c->table_ns / n : 0.0;
-    d.lg_scale = c->rics_backend == 2 ? (c->table_nlg - 1) / 8.0 : 0.0;
+    const bool table = config_has_table(c);
+    d.s_scale = table ? (double)c->table_ns / n : 0.0;
+    d.lg_scale = table ? (c->table_nlg - 1) / 8.0 : 0.0;
+    d.use_table = c->rics_backend == 2 ? 1 : 0;     // the MLP backend's lines decide at init
     d.s_scale_f = (float)d.s_scale;
     {
         const double k = 0.5 * d.lg_scale * log10(2.0);
@@ -203,16 +210,21 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
     // RICS table for u >= 0 at log10 gamma_i = 8 i/(nlg-1), s_j = (j + 1/2) L/ns, stored as
     // [ns][nlg] records {F(i), F(i+1), Ndot(i), Ndot(i+1)} (column i+1 clamped at the end)
     o.table.clear();
-    if (c->rics_backend == 2 && c->photon_field == 1) {
+    o.row_geo.clear();
+    if (table && c->photon_field == 1) {
         // the finite disk: built on the device by its quadrature (disk.hip)
         o.table.assign(4 * (size_t)c->table_nlg * c->table_ns, 0.0f);
-    } else if (c->rics_backend == 2) {
+    } else if (table) {
         const int nlg = c->table_nlg, ns = c->table_ns;
         std::vector<double> Fr(nlg), Nr(nlg);
         o.table.assign(4 * (size_t)nlg * ns, 0.0f);
+        o.row_geo.assign(3 * (size_t)ns, 0.0);
         for (int j = 0; j < ns; ++j) {
             const double s = (j + 0.5) * o.L_rstar / ns;
             const NodeGeo g = geometry_at(R, c->b_pole, cos_theta_at(R, s));
+            o.row_geo[3 * (size_t)j + 0] = g.b;
+            o.row_geo[3 * (size_t)j + 1] = g.mu;
+            o.row_geo[3 * (size_t)j + 2] = g.x;
             for (int i = 0; i < nlg; ++i) {
                 const double gam = pow(10.0, 8.0 * i / (nlg - 1));
                 const double u = sqrt(fmax(gam * gam - 1.0, 0.0));

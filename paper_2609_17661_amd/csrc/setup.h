@@ -20,10 +20,15 @@ struct LineHost {
     std::vector<float> nodes;          // 4 floats per node: b, mu, x, R_curv
     std::vector<double> rc;            // R_curv per node, double
     std::vector<float> table;          // F table then Ndot table, [ns][nlg]
+    std::vector<double> row_geo;       // b, mu, x at the table's row centres (radial table)
     std::vector<int32_t> layer_cell;   // local cells of the atmosphere layers
     std::vector<int32_t> layer_target; // their hydrostatic targets
     int64_t cap[4] = {0, 0, 0, 0};
 };
+
+// Whether the config gives every line a RICS table (TABLE backend, or the MLP
+// backend with its table fallback).
+bool config_has_table(const pic1d_config* cfg);
 
 // Validate cfg; returns an empty string if valid, else the reason.
 const char* validate_config(const pic1d_config* cfg);

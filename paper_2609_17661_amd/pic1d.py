@@ -43,7 +43,8 @@ class CConfig(ctypes.Structure):
                 ("nmax_over_n0", ctypes.c_double), ("atm_a0", ctypes.c_double), ("atm_h_cells", ctypes.c_double),
                 ("atm_T", ctypes.c_double), ("atm_cut", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("sort_interval", ctypes.c_int32), ("avg_start_step", ctypes.c_int32),
-                ("mlp_weights", ctypes.c_void_p), ("mlp_norm", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("mlp_weights", ctypes.c_void_p), ("mlp_norm", ctypes.c_void_p),
+                ("mlp_fallback_tol", ctypes.c_double), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
 
 
@@ -114,6 +115,8 @@ _SIGS = {
     "pic1d_set_field": (ctypes.c_int, [P, ctypes.c_int32, P]),
     "pic1d_set_step": (ctypes.c_int, [P, ctypes.c_int64]),
     "pic1d_rics_eval": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int64, P, P, P, P, P]),
+    "pic1d_rics_line_info": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int32)]),
     "pic1d_profile": (ctypes.c_int, [P, ctypes.c_int32]),
     "pic1d_profile_read": (ctypes.c_int, [P, ctypes.POINTER(CProfile)]),
     "pic1d_set_graph": (ctypes.c_int, [P, ctypes.c_int32]),
@@ -192,6 +195,7 @@ def make_cconfig(cfg):
     c.photon_field = PHOTON_FIELD[cfg["photon_field"]]
     c.seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
     c.sort_interval = int(cfg["sort_interval"])
+    c.mlp_fallback_tol = float(cfg["mlp_fallback_tol"])
     c.avg_start_step = int(cfg["avg_start_step"])
     return c, arr
 
@@ -333,6 +337,13 @@ class Pic1D:
         out = CTuneOut()
         self._check(self.lib.pic1d_autotune(self.h, int(trial_steps), ctypes.byref(out)))
         return {k: getattr(out, k) for k, _ in CTuneOut._fields_}
+
+    def rics_line_info(self, line=0):
+        """(surrogate error estimate on the line, whether the line uses its table)."""
+        err = ctypes.c_double(0.0)
+        tab = ctypes.c_int32(0)
+        self._check(self.lib.pic1d_rics_line_info(self.h, int(line), ctypes.byref(err), ctypes.byref(tab)))
+        return err.value, bool(tab.value)
 
     def rics_eval(self, line, s_cells, u):
         """F_hat, Ndot_hat, eps of the configured backend at device tensors s_cells, u (float32)."""

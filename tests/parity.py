@@ -168,11 +168,14 @@ def restrict(snap, keep):
     return dict(lines=lines, step=snap["step"])
 
 
-def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=None, check_field=True):
+def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=None, check_field=True,
+                 drop=None):
     """Advance the oracle from snap_before and compare with the GPU's snap_after.
 
     With check_field False the field after Ampere is not compared (for a
-    sample of the particles, whose current is not the whole line's).
+    sample of the particles, whose current is not the whole line's).  drop(li, s,
+    side, ids, cells, new) -> bool mask names particles to leave out of the
+    comparison; an id dropped on either side is dropped on both.
 
     Returns a report dict; raises AssertionError on an unexcused mismatch.
     """
@@ -214,6 +217,17 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
             G = Lg["parts"][s]
             O = st.parts[li][s]
             B = snap_before["lines"][li]["parts"][s]
+            if drop is not None:
+                bid = B["id"].astype(np.uint64)
+                gd = drop(li, s, "gpu", G["id"], G["cell"].astype(np.int64), ~np.isin(G["id"].astype(np.uint64), bid))
+                od = drop(li, s, "oracle", O["id"], np.floor(O["x"]).astype(np.int64),
+                          ~np.isin(O["id"].astype(np.uint64), bid))
+                gone = np.union1d(G["id"][gd].astype(np.uint64), O["id"][od].astype(np.uint64))
+                kg = ~np.isin(G["id"].astype(np.uint64), gone)
+                ko = ~np.isin(O["id"].astype(np.uint64), gone)
+                rep["dropped"] = rep.get("dropped", 0) + int((~kg).sum())
+                G = {k: v[kg] for k, v in G.items()}
+                O = {k: v[ko] for k, v in O.items()}
             before_ids = set(int(i) for i in B["id"])
             u_before = dict(zip((int(i) for i in B["id"]), B["u"].astype(np.float64)))
             gid = G["id"].astype(np.uint64)
@@ -344,7 +358,7 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
     return rep, st
 
 
-def sampled_compare(ocfg, snap_before, snap_after, n_sample, rng):
+def sampled_compare(ocfg, snap_before, snap_after, n_sample, rng, n_max=None):
     """compare_step on a sample of a full-size line (one line).
 
     Given the field, a particle's push, drag, event and conversion do not depend on
@@ -352,7 +366,15 @@ def sampled_compare(ocfg, snap_before, snap_after, n_sample, rng):
     counts of the atmosphere species.  The sample is therefore every atmosphere
     particle, n_sample seeded e-/e+ per lepton species, the pair members the sampled
     leptons can create this step (ids from the child stream) and the atmosphere
-    particles injected this step.  The field after Ampere is not compared."""
+    particles injected this step.  The field after Ampere is not compared.
+
+    With n_max given (a line at its density limit) the two couplings through cell
+    counts are taken from the whole line: the sample's pair members are compared
+    only in cells where the whole line's count at the step's start is below n_max
+    (elsewhere no pair is made; the GPU must have made none), and e-/e+ only in
+    cells that certainly annihilated nothing -- an end count of at most n_max - 2
+    with both e- and e+ left (annihilation stops at n_max - 1 or n_max, or where
+    one of them runs out).  The oracle steps the sample without annihilation."""
     L0, L1 = snap_before["lines"][0], snap_after["lines"][0]
     keep = []
     for s in range(4):
@@ -366,7 +388,27 @@ def sampled_compare(ocfg, snap_before, snap_after, n_sample, rng):
     injected = [np.setdiff1d(L1["parts"][s]["id"], L0["parts"][s]["id"]) for s in (2, 3)]
     keep_before = np.unique(np.concatenate(keep).astype(np.uint64))
     keep_after = np.unique(np.concatenate(keep + children + injected).astype(np.uint64))
+    drop = None
+    if n_max is not None:
+        n = int(L0["E"].shape[0])
+
+        def counts(L, species):
+            return sum(np.bincount(L["parts"][s]["cell"].astype(np.int64), minlength=n) for s in species)
+        blocked = counts(L0, range(4)) >= n_max
+        e1, p1 = counts(L1, (0,)), counts(L1, (1,))
+        unsafe = ~((counts(L1, range(4)) <= n_max - 2) & (e1 > 0) & (p1 > 0))
+        before_all = np.concatenate([L0["parts"][s]["id"] for s in (0, 1)]).astype(np.uint64)
+        for s in (0, 1):
+            made = ~np.isin(L1["parts"][s]["id"].astype(np.uint64), before_all)
+            cells = L1["parts"][s]["cell"][made].astype(np.int64)
+            assert not blocked[cells].any(), "a pair made in a cell at n_max"
+        ocfg = dict(ocfg, annihilation=False)
+
+        def drop(li, s, side, ids, cells, new):
+            if s >= 2:
+                return np.zeros(ids.shape, dtype=bool)
+            return unsafe[cells] | (new & blocked[cells])
     rep, st = compare_step(ocfg, restrict(snap_before, keep_before), restrict(snap_after, keep_after),
-                           check_field=False)
+                           check_field=False, drop=drop)
     rep["sampled"] = [int(k.size) for k in keep]
     return rep, st

@@ -1,4 +1,6 @@
 """Parity of the surrogate-network kernels (bfloat16 MFMA) with the FP64 oracle."""
+import math
+
 import numpy as np
 import pytest
 
@@ -288,3 +290,75 @@ def test_trained_network_beats_a_table_of_equal_storage():
     for k in (0, 1):
         assert np.median(e_net[:, k]) < 0.5 * np.median(e_tab[:, k])
         assert np.quantile(e_net[:, k], 0.99) < 0.1 * np.quantile(e_tab[:, k], 0.99)
+
+
+# ---------------------------------------------------------------------------
+# the table as the network's fallback, per line
+# ---------------------------------------------------------------------------
+def _fallback_cfg(tol, radii, n_cells=96, ppc=12):
+    p, norm = _pusher_network(61)
+    lines = [dict(r_eq=r, n_cells=n_cells, ppc_init=ppc, init="hot", init_gamma_max=3e3,
+                  capacity=[200_000, 200_000, 50_000, 50_000]) for r in radii]
+    return dict(rics="mlp", kT_keV=0.5, j_twist=0.5, ppc0=float(ppc), seed=7, pairs=True, table_nlg=64, table_ns=48,
+                mlp_params=p, mlp_norm=norm, mlp_fallback_tol=tol, lines=lines)
+
+
+def _oracle_estimates(cfg):
+    from oracle import pic
+
+    from . import parity
+    st = pic.State(parity.oracle_config(cfg))
+    return [ln.mlp_error for ln in st.lines], [ln.use_table for ln in st.lines]
+
+
+def test_fallback_estimates_match_oracle():
+    """Per-line error estimates of the network (largest relative error of F and Ndot on the
+    table nodes) from the GPU's bfloat16 network against the oracle's float64 one."""
+    from paper_2609_17661_amd import Pic1D
+    radii = [4.0, 10.0, 40.0]
+    cfg = _fallback_cfg(1e30, radii)
+    e_o, _ = _oracle_estimates(cfg)
+    _print("fallback estimates, oracle", e_o)
+    sim = Pic1D(cfg)
+    info = [sim.rics_line_info(li) for li in range(len(radii))]
+    _print("fallback estimates, GPU", info)
+    for (e, tab), eo in zip(info, e_o):
+        assert not tab
+        # network outputs within OUT_TOL (relative ln(10) std OUT_TOL after 10^o), float32
+        # geometry and the factor (gamma mu - u) near the attractor: 1e-3 relative is ample
+        assert abs(e - eo) <= 1e-3 * eo + 1e-6, (e, eo)
+    sim.close()
+
+
+def test_mixed_step_parity_with_table_fallback():
+    """Two lines, a tolerance between their estimates: one steps with the network, the
+    other with its table, in the same launch, each matched against the oracle."""
+    from paper_2609_17661_amd import Pic1D
+
+    from . import parity
+    radii = [4.0, 40.0]
+    e_o, _ = _oracle_estimates(_fallback_cfg(1e30, radii))
+    assert e_o[0] != e_o[1]
+    tol = math.sqrt(e_o[0] * e_o[1])
+    cfg = _fallback_cfg(tol, radii)
+    ocfg = parity.oracle_config(cfg)
+    _, use_o = _oracle_estimates(cfg)
+    sim = Pic1D(cfg)
+    use_g = [sim.rics_line_info(li)[1] for li in range(len(radii))]
+    _print("fallback tol", tol, "tables (oracle, GPU)", use_o, use_g)
+    assert use_g == use_o and sorted(use_g) == [False, True]
+    total = dict(compared=0, excused=0)
+    for k in range(3):
+        before = parity.snapshot(sim)
+        sim.step(1)
+        after = parity.snapshot(sim)
+        rep, st = parity.compare_step(ocfg, before, after)
+        _print(f"  step {k}: {rep}")
+        total["compared"] += rep["compared"]
+        total["excused"] += rep["excused"]
+        sim.step(2)
+    assert total["compared"] > 0
+    assert total["excused"] <= max(3, 1e-3 * total["compared"])
+    for li in range(len(radii)):
+        assert sim.moments(li)["gauss_residual"] <= 1e-6
+    sim.close()

@@ -204,3 +204,85 @@ def test_pic_step_with_the_surrogate_conserves_charge():
         pic.step(st, stats)
     assert pic.gauss_residual(st, 0) < 1e-12
     assert st.counters[0]['events'] > 0
+
+
+# ---------------------------------------------------------------------------
+# the surrogate's error estimate on a line (the decision for its table fallback)
+# ---------------------------------------------------------------------------
+def _line_rows(R, b_pole, n_s):
+    from oracle import geometry
+    L = geometry.line_length(R)
+    c = geometry.cos_of_s(R, (np.arange(n_s) + 0.5) / n_s * L)
+    return geometry.field_b(b_pole, R, c), geometry.photon_mu(c), geometry.radius(R, c)
+
+
+def _exact(scale_F=1.0, scale_N=1.0):
+    def f(u, sl, b, mu, x, kT):
+        return scale_F * rics.drag_force(u, b, mu, x, kT), scale_N * rics.scatter_rate(u, b, mu, x, kT)
+    return f
+
+
+def test_error_estimate_of_scaled_definitions_is_the_scale():
+    b, mu, x = _line_rows(10.0, 10.0, 16)
+    kw = dict(n_lg=64, kT=0.5, h=1e-3)
+    assert mlp.line_error_estimate(None, None, b, mu, x, surrogate=_exact(), **kw) == 0.0
+    e = mlp.line_error_estimate(None, None, b, mu, x, surrogate=_exact(1.0 + 3e-3, 1.0 - 1e-3), **kw)
+    assert abs(e - 3e-3) < 1e-12
+    e = mlp.line_error_estimate(None, None, b, mu, x, surrogate=_exact(1.0, 1.0 + 7e-3), **kw)
+    assert abs(e - 7e-3) < 1e-12
+    # a force of the wrong sign is off by 2
+    assert abs(mlp.line_error_estimate(None, None, b, mu, x, surrogate=_exact(-1.0), **kw) - 2.0) < 1e-12
+
+
+def test_error_estimate_counts_significant_nodes_only():
+    b, mu, x = _line_rows(10.0, 10.0, 16)
+    # with a vanishing step no node moves u or scatters enough to count
+    assert mlp.line_error_estimate(None, None, b, mu, x, 64, 0.5, 1e-40, surrogate=_exact(5.0, 5.0)) == 0.0
+    # non-finite output: no trust
+    def nan_at_top(u, sl, bj, muj, xj, kT):
+        F, N = _exact()(u, sl, bj, muj, xj, kT)
+        return np.where(u == u.max(), np.nan, F), N
+    e = mlp.line_error_estimate(None, None, b, mu, x, 64, 0.5, 1e3, surrogate=nan_at_top)
+    assert e == np.inf
+
+
+def test_error_estimate_feeds_each_row_its_own_arc_fraction():
+    """A surrogate that rebuilds the geometry from s/L alone (the R_max = 4 line) is exact
+    on that line's rows, and far off when the rows are handed in reversed."""
+    from oracle import geometry
+    R, bp, n_s = mlp.R_TRAIN, 10.0, 24
+
+    def from_sl(u, sl, bj, muj, xj, kT):
+        c = geometry.cos_of_s(R, sl * geometry.line_length(R))
+        bb, mm, xx = geometry.field_b(bp, R, c), geometry.photon_mu(c), geometry.radius(R, c)
+        return rics.drag_force(u, bb, mm, xx, kT), rics.scatter_rate(u, bb, mm, xx, kT)
+    b, mu, x = _line_rows(R, bp, n_s)
+    assert mlp.line_error_estimate(None, None, b, mu, x, 48, 0.5, 1e-3, surrogate=from_sl) < 1e-9
+    e = mlp.line_error_estimate(None, None, b[::-1], mu[::-1], x[::-1], 48, 0.5, 1e-3, surrogate=from_sl)
+    assert e > 0.5
+
+
+def test_fallback_decision_per_line():
+    """With a tolerance between two lines' estimates, the line above it takes its table."""
+    from oracle import pic
+    rng = np.random.default_rng(4)
+    parts = []
+    for li, (o, i) in enumerate(mlp.LAYERS):
+        s = 0.15 if li == len(mlp.LAYERS) - 1 else 1.0
+        parts.append((rng.uniform(-1, 1, (o, i)) * s * mlp.glorot_bound(o, i), rng.uniform(-0.1, 0.1, o)))
+    p = mlp.pack(parts)
+    _, O, _ = mlp.training_samples(seed=4, n=2048)
+    mean, std = mlp.normalisation(O)
+    base = dict(rics="mlp", mlp_params=p, mlp_norm=np.concatenate([mean, std]), table_nlg=32, table_ns=16,
+                lines=[dict(r_eq=4.0, n_cells=64), dict(r_eq=40.0, n_cells=64)])
+    st = pic.State(pic.make_config(mlp_fallback_tol=1e30, **base))
+    e = [ln.mlp_error for ln in st.lines]
+    assert all(np.isfinite(v) and v > 0 for v in e) and e[0] != e[1]
+    assert not any(ln.use_table for ln in st.lines)
+    tol = math.sqrt(e[0] * e[1])
+    st = pic.State(pic.make_config(mlp_fallback_tol=tol, **base))
+    assert [ln.use_table for ln in st.lines] == [v > tol for v in e]
+    assert [ln.mlp_error for ln in st.lines] == e
+    # without a tolerance no estimate is made and every line uses the network
+    st = pic.State(pic.make_config(**base))
+    assert all(ln.mlp_error is None and not ln.use_table for ln in st.lines)
