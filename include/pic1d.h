@@ -299,17 +299,28 @@ typedef struct {
     int32_t n_trials;            /* launch shapes timed                            */
     double ms_per_step_before;   /* with the shape the state had                   */
     double ms_per_step_after;    /* with the chosen shape                          */
+    int32_t push_ppt;            /* particles per lane of a particle-kernel tile   */
+    int32_t deposit_window;      /* cells of a wavefront's LDS deposit window      */
 } pic1d_tune_out;
 
 /* Autotuner of the launch shape: times trial_steps real steps (at least one
- * sort cycle) for each candidate -- push blocks per CU in {1,2,3,4,6,8}, the
- * XCD-aware tile walk on/off, sort_interval in {1,2,5,10,25,50,100} -- one knob at a
- * time, and keeps the fastest; a block count other than the starting one must
- * beat it again when the two are timed alternately twice.  The trial steps
- * advance the simulation; the
+ * sort cycle) for each candidate -- the particle kernel's tile shape (4, 8 or
+ * 16 particles per lane; the deposit window, 128 or 64 cells for the TABLE
+ * backend, 32 or 64 for OFF and EXACT, wherever that shape is built), push
+ * blocks per CU in {1,2,3,4,6,8}, the XCD-aware tile walk on/off, sort_interval
+ * in {1,2,5,10,25,50,100} -- one knob at a time, and keeps the fastest; a tile
+ * shape or block count other than the starting one must beat it again when the
+ * two are timed alternately twice.  The trial steps advance the simulation; the
  * physics does not depend on these choices (particle order and launch shape do
  * not change any result).  Errors: EINVAL, ESTATE, ECAPACITY, ENONFINITE. */
 int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out);
+
+/* Set the particle kernel's launch shape directly: blocks per CU (1..32),
+ * particles per lane of a tile (4, 8, 16) and the deposit window in cells (the
+ * combinations pic1d_autotune lists; the MLP backend has 8 and 32 only).  The
+ * results do not depend on it.  Errors: EINVAL (a shape that is not built),
+ * ESTATE. */
+int pic1d_set_push_shape(pic1d_state* st, int32_t blocks_per_cu, int32_t ppt, int32_t window);
 
 /* The surrogate's error estimate on one line and whether the line uses its
  * table instead (MLP backend with mlp_fallback_tol > 0; otherwise *error = -1 and

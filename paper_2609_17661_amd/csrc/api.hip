@@ -104,6 +104,8 @@ struct pic1d_state {
     // launch shape (tunable) and captured step graphs
     int xcd_walk = 1;
     int push_bpc = 0;                              // push blocks per CU
+    int ppt = PUSH_PPT_DEFAULT;                    // particles per lane per tile of the push
+    int ww = 0;                                    // deposit window of the push (cells)
     int graph_steps = 0;                           // requested steps per graph; 0 = eager
     int graph_len = 0;                             // steps per graph (a multiple of sort_interval)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // by the live buffer set at the graph's start
@@ -246,12 +248,37 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->mlp_err_bits = cv.take<unsigned int>(L.mlp_fallback ? L.n_lines : 1);
 }
 
+// The particle kernel of a backend at a tile shape (particles per lane, deposit
+// window in cells), or null where that shape is not built.
+const void* push_kernel(int backend, int ppt, int ww) {
+    switch (backend) {
+        case RICS_OFF:
+            if (ww == 32) return ppt == 4 ? (const void*)k_push<RICS_OFF, 4, 32> : ppt == 8 ? (const void*)k_push<RICS_OFF, 8, 32>
+                               : ppt == 16 ? (const void*)k_push<RICS_OFF, 16, 32> : nullptr;
+            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_OFF, 8, 64> : nullptr;
+        case RICS_EXACT:
+            if (ww == 32) return ppt == 4 ? (const void*)k_push<RICS_EXACT, 4, 32> : ppt == 8 ? (const void*)k_push<RICS_EXACT, 8, 32>
+                               : ppt == 16 ? (const void*)k_push<RICS_EXACT, 16, 32> : nullptr;
+            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_EXACT, 8, 64> : nullptr;
+        case RICS_TABLE:
+            if (ww == 128) return ppt == 4 ? (const void*)k_push<RICS_TABLE, 4, 128> : ppt == 8 ? (const void*)k_push<RICS_TABLE, 8, 128>
+                                : ppt == 16 ? (const void*)k_push<RICS_TABLE, 16, 128> : nullptr;
+            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_TABLE, 8, 64> : nullptr;
+        case RICS_MLP:
+            return (ww == 32 && ppt == 8) ? (const void*)k_push<RICS_MLP, 8, 32> : nullptr;
+        default:
+            return nullptr;
+    }
+}
+
+int default_window(int backend) { return backend == RICS_TABLE ? 128 : 32; }
+
 PushArgs push_args(pic1d_state* st) {
     PushArgs a{};
     const int b = st->cur;
     a.cell = st->cell[b]; a.off = st->off[b]; a.u = st->u[b]; a.id = st->id[b];
     a.seg_base = st->seg_base; a.seg_cap = st->seg_cap; a.n_cur = st->n_cur; a.alloc = st->alloc;
-    a.tile_prefix = st->tile_prefix; a.nseg = st->lay.nseg;
+    a.tile_prefix = st->tile_prefix; a.nseg = st->lay.nseg; a.tile = 64 * st->ppt;
     a.nlg = st->cfg.table_nlg; a.ns = st->cfg.table_ns;
     a.pairs = st->cfg.pairs; a.conversion = st->cfg.conversion;
     a.gravity = st->cfg.atmosphere && st->cfg.gravity;
@@ -275,7 +302,7 @@ BookArgs book_args(pic1d_state* st) {
     BookArgs b{};
     b.n_photons = st->n_photons;
     b.n_cur = st->n_cur; b.alloc = st->alloc; b.seg_cap = st->seg_cap; b.tile_prefix = st->tile_prefix;
-    b.nseg = st->lay.nseg; b.sc = st->sc;
+    b.nseg = st->lay.nseg; b.tile = 64 * st->ppt; b.sc = st->sc;
     return b;
 }
 
@@ -311,14 +338,12 @@ void prof_collect(pic1d_state* st) {
 
 int launch_push(pic1d_state* st) {
     PushArgs a = push_args(st);
+    const void* kp = push_kernel(st->backend, st->ppt, st->ww);
+    if (!kp) return fail(st, PIC1D_EINVAL, "push shape not built");
+    void* args[] = {&a};
     const int pk = prof_begin(st, 0);
-    switch (st->backend) {
-        case RICS_OFF: hipLaunchKernelGGL(k_push<RICS_OFF>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
-        case RICS_EXACT: hipLaunchKernelGGL(k_push<RICS_EXACT>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
-        case RICS_TABLE: hipLaunchKernelGGL(k_push<RICS_TABLE>, dim3(st->push_blocks), dim3(PUSH_TPB), 0, st->stream, a); break;
-        case RICS_MLP: hipLaunchKernelGGL(k_push<RICS_MLP>, dim3(st->push_blocks), dim3(PUSH_TPB_MLP), 0, st->stream, a); break;
-        default: return fail(st, PIC1D_EINVAL, "unknown RICS backend");
-    }
+    HIP_TRY(st, hipLaunchKernel(kp, dim3(st->push_blocks), dim3(st->backend == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB),
+                                args, 0, st->stream));
     prof_end(st, pk);
     return PIC1D_OK;
 }
@@ -334,7 +359,7 @@ int launch_hist(pic1d_state* st) {
     // recount H[step & 1] from the live particles
     HistArgs h{};
     h.cell = st->cell[st->cur]; h.seg_base = st->seg_base; h.n_cur = st->n_cur; h.tile_prefix = st->tile_prefix;
-    h.nseg = st->lay.nseg; h.lines = st->dlines; h.hist = st->hist[st->host_step & 1];
+    h.nseg = st->lay.nseg; h.tile = 64 * st->ppt; h.lines = st->dlines; h.hist = st->hist[st->host_step & 1];
     HIP_TRY(st, hipMemsetAsync(h.hist, 0, 4 * sizeof(int32_t) * (size_t)st->lay.n_cells, st->stream));
     hipLaunchKernelGGL(k_hist, dim3(st->aux_blocks), dim3(PUSH_TPB), 0, st->stream, h);
     return PIC1D_OK;
@@ -347,7 +372,7 @@ int launch_sort(pic1d_state* st) {
     s.cell2 = st->cell[o]; s.off2 = st->off[o]; s.u2 = st->u[o]; s.id2 = st->id[o];
     s.seg_base = st->seg_base; s.seg_cap = st->seg_cap; s.n_cur = st->n_cur; s.alloc = st->alloc;
     s.tile_prefix = st->tile_prefix;
-    s.nseg = st->lay.nseg; s.lines = st->dlines; s.hist[0] = st->hist[0]; s.hist[1] = st->hist[1];
+    s.nseg = st->lay.nseg; s.tile = 64 * st->ppt; s.lines = st->dlines; s.hist[0] = st->hist[0]; s.hist[1] = st->hist[1];
     s.bins = st->bins; s.chunk_sum = st->chunk_sum; s.chunk_line = st->chunk_line; s.line_chunk0 = st->line_chunk0;
     s.n_chunks = st->lay.n_chunks; s.n_bins = SORT_SUB * st->lay.n_cells;
     s.new_count = st->new_count; s.sc = st->sc;
@@ -433,9 +458,9 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
     }
     st->n_cu = prop.multiProcessorCount;
     int occ = 0;
-    const void* kp = st->backend == RICS_OFF ? (const void*)k_push<RICS_OFF>
-                   : st->backend == RICS_EXACT ? (const void*)k_push<RICS_EXACT>
-                   : st->backend == RICS_MLP ? (const void*)k_push<RICS_MLP> : (const void*)k_push<RICS_TABLE>;
+    st->ppt = PUSH_PPT_DEFAULT;
+    st->ww = default_window(st->backend);
+    const void* kp = push_kernel(st->backend, st->ppt, st->ww);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, st->backend == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB, 0);
     occ = std::max(1, std::min(occ, 8));
     st->push_blocks = st->n_cu * occ;
@@ -767,6 +792,29 @@ int pic1d_set_graph(pic1d_state* st, int32_t steps_per_graph) {
     return PIC1D_OK;
 }
 
+// Tile shape and block count of the particle kernel.  A new tile size re-plans the
+// tiles of the live particles (the plan is in units of tiles); captured graphs hold
+// the old arguments and are dropped.
+int set_push_shape(pic1d_state* st, int blocks_per_cu, int ppt, int ww) {
+    st->drop_graphs();
+    st->push_blocks = st->n_cu * blocks_per_cu;
+    const bool retile = ppt != st->ppt;
+    st->ppt = ppt;
+    st->ww = ww;
+    if (retile) {
+        if (int rc = launch_plan(st, 0)) return rc;
+        HIP_TRY(st, hipGetLastError());
+    }
+    return PIC1D_OK;
+}
+
+int pic1d_set_push_shape(pic1d_state* st, int32_t blocks_per_cu, int32_t ppt, int32_t window) {
+    if (!st || blocks_per_cu < 1 || blocks_per_cu > 32) return fail(st, PIC1D_EINVAL, "bad arguments");
+    if (st->frozen) return fail(st, PIC1D_ESTATE, "state frozen by an earlier error");
+    if (!push_kernel(st->backend, ppt, window)) return fail(st, PIC1D_EINVAL, "push shape not built");
+    return set_push_shape(st, blocks_per_cu, ppt, window);
+}
+
 int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out) {
     if (!st || trial_steps < 1 || !out) return fail(st, PIC1D_EINVAL, "bad arguments");
     if (st->frozen) return fail(st, PIC1D_ESTATE, "state frozen by an earlier error");
@@ -798,6 +846,36 @@ int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out) {
     int rc = measure(base);
     double best = base;
     const int occ = std::max(1, st->push_blocks / std::max(st->n_cu, 1));
+    // 0. tile shape of the particle kernel: particles per lane and deposit window
+    {
+        const int ppt0 = st->ppt, ww0 = st->ww;
+        int best_ppt = ppt0, best_ww = ww0;
+        double best_shape = base;
+        const int cand_ppt[] = {4, 8, 16};
+        const int cand_ww[] = {default_window(st->backend), 64};
+        for (int p : cand_ppt)
+            for (int w : cand_ww) {
+                if (rc || (p == ppt0 && w == ww0) || !push_kernel(st->backend, p, w)) continue;
+                rc = set_push_shape(st, occ, p, w);
+                double t = 0.0;
+                if (!rc) rc = measure(t);
+                if (!rc && t < best_shape) { best_shape = t; best_ppt = p; best_ww = w; }
+            }
+        // the winner has to beat the starting shape again, timed alternately twice each
+        if (!rc && (best_ppt != ppt0 || best_ww != ww0)) {
+            double ta = 0.0, tb = 0.0;
+            for (int rep = 0; rep < 2 && !rc; ++rep)
+                for (int which = 0; which < 2 && !rc; ++which) {
+                    rc = which ? set_push_shape(st, occ, best_ppt, best_ww) : set_push_shape(st, occ, ppt0, ww0);
+                    double t = 0.0;
+                    if (!rc) rc = measure(t);
+                    (which ? tb : ta) += t;
+                }
+            if (!rc && ta <= tb) { best_ppt = ppt0; best_ww = ww0; }
+            if (!rc) best = 0.5 * std::min(ta, tb);
+        }
+        if (!rc) rc = set_push_shape(st, occ, best_ppt, best_ww);
+    }
     // 1. push blocks per CU
     const int bpc0 = occ;
     int best_bpc = bpc0;
@@ -857,6 +935,8 @@ int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out) {
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     out->push_blocks_per_cu = st->push_blocks / std::max(st->n_cu, 1);
+    out->push_ppt = st->ppt;
+    out->deposit_window = st->ww;
     out->xcd_walk = st->xcd_walk;
     out->sort_interval = st->cfg.sort_interval;
     out->n_trials = trials;
@@ -891,6 +971,7 @@ int pic1d_moments(pic1d_state* st, int32_t line, int32_t flags, pic1d_moments_ou
     MomArgs m{};
     m.cell = st->cell[st->cur]; m.off = st->off[st->cur]; m.u = st->u[st->cur];
     m.seg_base = st->seg_base; m.n_cur = st->n_cur; m.tile_prefix = st->tile_prefix; m.nseg = st->lay.nseg;
+    m.tile = 64 * st->ppt;
     m.line = line; m.lines = st->dlines; m.E = st->E; m.rho = st->rho; m.out = st->mom_out;
     m.kin = st->mom_kin; m.part = st->mom_out + 8;
     const double sign[4] = {-1.0, 1.0, -1.0, 1.0};

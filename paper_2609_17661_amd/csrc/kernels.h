@@ -11,10 +11,10 @@ enum { RICS_OFF = 0, RICS_EXACT = 1, RICS_TABLE = 2, RICS_MLP = 3 };
 constexpr int PUSH_TPB = 256;                   // threads per block of the particle kernels
 constexpr int PUSH_TPB_MLP = 256;               // ... with the surrogate network: one block per CU (its
                                                 // weights fill the LDS), one wavefront per SIMD
-constexpr int PUSH_PPT = 8;                     // consecutive particles per thread per tile
+constexpr int PUSH_PPT_DEFAULT = 8;             // consecutive particles per thread per tile: 4, 8 or 16
+                                                // (a tile, 64 ppt particles, is one wavefront's work item;
+                                                // the other particle kernels take a tile per block)
 constexpr int CNT_REPL = 64;                    // replicas of every counter (spreads same-address atomics)
-constexpr int PUSH_TILE = 64 * PUSH_PPT;        // particles per tile: one wavefront's work item
-constexpr int AUX_PPT = PUSH_TILE / PUSH_TPB;   // particles per thread when a block takes a tile
 constexpr int SORT_SUB = 8;                     // sort key: cell and offset in eighths of a cell
 constexpr int SCAN_CELLS = 256;                 // cells per chunk of the sort's scan (one block)
 
@@ -43,6 +43,7 @@ struct PushArgs {
     int32_t* alloc;
     const int32_t* tile_prefix;
     int32_t nseg;
+    int32_t tile;              // particles per tile (64 ppt)
     int32_t nlg, ns;
     int32_t pairs, conversion, gravity;
     const LineDev* lines;
@@ -117,6 +118,7 @@ struct BookArgs {
     const int32_t* seg_cap;
     int32_t* tile_prefix;
     int32_t nseg;
+    int32_t tile;              // particles per tile (64 ppt)
     DevScalars* sc;
 };
 
@@ -190,6 +192,7 @@ struct SortArgs {
     int32_t* alloc;
     const int32_t* tile_prefix;
     int32_t nseg;
+    int32_t tile;              // particles per tile (64 ppt)
     const LineDev* lines;
     int32_t* hist[2];          // counts per cell and species; current = hist[step & 1]
     int4* bins;                // [cells * SORT_SUB]: counts, then cursors, per species
@@ -221,6 +224,7 @@ struct HistArgs {
     const int32_t* n_cur;
     const int32_t* tile_prefix;
     int32_t nseg;
+    int32_t tile;              // particles per tile (64 ppt)
     const LineDev* lines;
     int32_t* hist;
 };
@@ -233,6 +237,7 @@ struct MomArgs {
     const int32_t* n_cur;
     const int32_t* tile_prefix;
     int32_t nseg;
+    int32_t tile;              // particles per tile (64 ppt)
     int32_t line;
     const LineDev* lines;
     const double* E;
@@ -261,7 +266,7 @@ void gauss_legendre(int n, double* x, double* w);
 hipError_t launch_disk_table(const DiskTableArgs& a, hipStream_t s);
 constexpr int DISK_N_C = 24, DISK_N_PHI = 24;
 
-template <int BACKEND> __global__ void k_push(PushArgs a);
+template <int BACKEND, int PPT, int WW> __global__ void k_push(PushArgs a);
 __global__ void k_mlp_pack(const float* p, bf16x8* ft, bf16x8* bt, float* bias);
 // The surrogate's error estimate on every line: the largest relative error of
 // F_hat and Ndot_hat against the float64 closed forms over the line's table nodes,

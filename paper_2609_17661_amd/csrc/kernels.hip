@@ -12,6 +12,8 @@
 //                 eighth of a cell) per segment, dropping absorbed particles
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "rics_dev.h"
 
@@ -538,16 +540,48 @@ __device__ __forceinline__ void counts_flush(unsigned long long* counters, int l
     c = Counts();
 }
 
-// Deposit window of one wavefront (cells) and waves per SIMD of the particle
-// kernel, per backend.  A wavefront's LDS is its staged tile (6 KB) plus the
-// window (12 bytes per cell): with 128 cells five 256-thread blocks fit a CU
-// (five waves per SIMD, what the table backend's registers allow), with 32 cells
-// six (the closed-form and field-only backends, in 80 registers with at most a
-// few spilled).  Tiles whose
-// cells span more than the window deposit through global atomics instead.
-constexpr int push_ww(int backend) { return backend == RICS_TABLE ? 128 : 32; }
+// Waves per SIMD the particle kernel is compiled for, per backend.  A wavefront's
+// LDS is its staged tile (768 bytes per particle per lane: 6 KB at 8) plus its
+// deposit window (12 bytes per cell): at 8 particles per lane and 128 cells five
+// 256-thread blocks fit a CU (five waves per SIMD, what the table backend's
+// registers allow), at 32 cells six (the closed-form and field-only backends, in
+// 80 registers with at most a few spilled).  The tile (4, 8 or 16 particles per
+// lane) and the window (cells) are template parameters picked by the autotuner;
+// tiles whose cells span more than the window deposit through global atomics.
 constexpr int push_waves(int backend) {
     return backend == RICS_MLP ? 1 : backend == RICS_TABLE ? 5 : 6;
+}
+
+// Sorting network on PPT keys (ascending): the 19-comparator network for 8, five
+// comparators for 4, Batcher's bitonic network for 16.
+template <int PPT>
+__device__ __forceinline__ void sort_keys(uint32_t* k) {
+    auto cx = [&](int i, int j) {
+        const uint32_t x = k[i], y = k[j];
+        k[i] = min(x, y);
+        k[j] = max(x, y);
+    };
+    if constexpr (PPT == 4) {
+        cx(0, 1); cx(2, 3); cx(0, 2); cx(1, 3); cx(1, 2);
+    } else if constexpr (PPT == 8) {
+        constexpr int NET[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
+                                    {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+        for (int e = 0; e < 19; ++e) cx(NET[e][0], NET[e][1]);
+    } else {
+#pragma unroll
+        for (int size = 2; size <= PPT; size <<= 1)
+#pragma unroll
+            for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    const int j = i ^ stride;
+                    if (j > i) {
+                        if ((i & size) == 0) cx(i, j);
+                        else cx(j, i);
+                    }
+                }
+    }
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -555,24 +589,25 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// The particle kernel.  Work is split into tiles of PUSH_TILE consecutive particles
-// of one (line, species) segment, one tile per wavefront at a time, PUSH_PPT
+// The particle kernel.  Work is split into tiles of 64 PPT consecutive particles
+// of one (line, species) segment, one tile per wavefront at a time, PPT
 // consecutive particles per lane (128-bit loads and stores).  Each lane
 // accumulates its deposit and new-cell counts over runs of particles in the same
 // cell (three cells wide: the run's cell and its neighbours); each wavefront
 // merges its lanes in a private LDS window and flushes the window to the global
 // fixed-point current with one atomic per touched cell.  No block-level
 // synchronisation.
-template <int BACKEND>
+template <int BACKEND, int PPT, int WW>
 __global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB)
 __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a) {
-    constexpr int WW = push_ww(BACKEND);
+    static_assert(PPT == 4 || PPT == 8 || PPT == 16, "4, 8 or 16 particles per lane");
+    constexpr int TILE = 64 * PPT;
     constexpr int TPB = BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB;
     __shared__ unsigned long long sJ[TPB / 64][WW];
     __shared__ int sH[TPB / 64][WW];
-    __shared__ int sPc[TPB / 64][PUSH_PPT][64];      // the wave's tile: cell, offset, momentum
-    __shared__ float sPo[TPB / 64][PUSH_PPT][64];
-    __shared__ float sPu[TPB / 64][PUSH_PPT][64];
+    __shared__ int sPc[TPB / 64][PPT][64];      // the wave's tile: cell, offset, momentum
+    __shared__ float sPo[TPB / 64][PPT][64];
+    __shared__ float sPu[TPB / 64][PPT][64];
     // surrogate weights, staged once per block (the network runs on them for every particle)
     __shared__ bf16x8 sW[BACKEND == RICS_MLP ? FT_TOTAL * 64 : 1];
     __shared__ float sWb[BACKEND == RICS_MLP ? MLP_BIAS : 1];
@@ -600,8 +635,8 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
     int f_seg = 0, f_ib = 0, f_nv = 0;
     bool f_full = false;
     int64_t f_base = 0;
-    int4 fc[PUSH_PPT / 4];
-    float4 fo[PUSH_PPT / 4], fu[PUSH_PPT / 4];
+    int4 fc[PPT / 4];
+    float4 fo[PPT / 4], fu[PPT / 4];
     // (every call assigns all fetched values, so that none stays live across the loop)
     auto fetch = [&](int t) {
         const bool have = t < ww.end;
@@ -612,18 +647,18 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
         }
         f_seg = seg;
         f_base = kconst(a.seg_base)[seg];
-        // this lane's PUSH_PPT consecutive particles (vector loads; slots up to the
+        // this lane's PPT consecutive particles (vector loads; slots up to the
         // capacity, a multiple of 256, always exist)
-        const int t0 = (t - seg_t0) * PUSH_TILE;
+        const int t0 = (t - seg_t0) * TILE;
         const int ncur = kconst(a.n_cur)[seg];
-        f_full = have && ncur - t0 >= PUSH_TILE;        // wave-uniform
-        f_ib = t0 + lane * PUSH_PPT;
-        f_nv = have ? max(0, min(PUSH_PPT, ncur - f_ib)) : 0;
+        f_full = have && ncur - t0 >= TILE;        // wave-uniform
+        f_ib = t0 + lane * PPT;
+        f_nv = have ? max(0, min(PPT, ncur - f_ib)) : 0;
         const int4* cp = reinterpret_cast<const int4*>(a.cell + f_base + f_ib);
         const float4* op = reinterpret_cast<const float4*>(a.off + f_base + f_ib);
         const float4* up = reinterpret_cast<const float4*>(a.u + f_base + f_ib);
 #pragma unroll
-        for (int h = 0; h < PUSH_PPT / 4; ++h) {
+        for (int h = 0; h < PPT / 4; ++h) {
             fc[h] = make_int4(DEAD_CELL, DEAD_CELL, DEAD_CELL, DEAD_CELL);
             fo[h] = make_float4(0.5f, 0.5f, 0.5f, 0.5f);
             fu[h] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -647,10 +682,10 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
         // smallest as signed, so neither bound sees it.
         unsigned lo_u = 0xffffffffu;
         int hi_s = INT32_MIN;
-        int cst[PUSH_PPT];
+        int cst[PPT];
         auto stage = [&](auto full) {
 #pragma unroll
-            for (int h = 0; h < PUSH_PPT / 4; ++h) {
+            for (int h = 0; h < PPT / 4; ++h) {
                 const int4 ci = fc[h];
                 const float4 oi = fo[h], ui = fu[h];
                 const int cv[4] = {ci.x, ci.y, ci.z, ci.w};
@@ -683,32 +718,30 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
         else cache_load<BACKEND>(cc, a, L, qmC, first);
         // The order in which the lane visits its slots: by cell (dead slots last), so
         // that the run accumulator and the cell cache see each cell once however the
-        // particles of a cell are ordered in memory.  A 19-comparator sorting network
-        // on keys (cell - first) * 8 + slot; the slot order is packed in 3-bit fields.
+        // particles of a cell are ordered in memory.  A sorting network on keys
+        // (cell - first) * 2^VB + slot; the slot order is packed in VB-bit fields.
         // Slots already in that order (as unsigned, DEAD_CELL is the largest) keep
         // it; the network runs when any lane of the wavefront needs it.
-        static_assert(PUSH_PPT == 8, "the visit order packs 8 slots in 3-bit fields");
-        constexpr uint32_t IN_ORDER = 0u | 1u << 3 | 2u << 6 | 3u << 9 | 4u << 12 | 5u << 15 | 6u << 18 | 7u << 21;
-        uint32_t visit = IN_ORDER;
+        constexpr int VB = PPT == 4 ? 2 : PPT == 8 ? 3 : 4;
+        using Visit = std::conditional_t<PPT == 16, uint64_t, uint32_t>;
+        constexpr Visit IN_ORDER = [] {
+            Visit v = 0;
+            for (int q = 0; q < PPT; ++q) v |= (Visit)q << (VB * q);
+            return v;
+        }();
+        Visit visit = IN_ORDER;
         bool ordered = true;
 #pragma unroll
-        for (int q = 1; q < PUSH_PPT; ++q) ordered = ordered && (uint32_t)cst[q] >= (uint32_t)cst[q - 1];
+        for (int q = 1; q < PPT; ++q) ordered = ordered && (uint32_t)cst[q] >= (uint32_t)cst[q - 1];
         if (__ballot(!ordered) != 0ull) {
             visit = 0;
-            uint32_t k[PUSH_PPT];
+            uint32_t k[PPT];
 #pragma unroll
-            for (int q = 0; q < PUSH_PPT; ++q)
-                k[q] = (cst[q] == DEAD_CELL ? 0xfffffff8u : (uint32_t)(cst[q] - first) << 3) | (uint32_t)q;
-            constexpr int NET[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
-                                        {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+            for (int q = 0; q < PPT; ++q)
+                k[q] = (cst[q] == DEAD_CELL ? (0xffffffffu << VB) : (uint32_t)(cst[q] - first) << VB) | (uint32_t)q;
+            sort_keys<PPT>(k);
 #pragma unroll
-            for (int e = 0; e < 19; ++e) {
-                const uint32_t x = k[NET[e][0]], y = k[NET[e][1]];
-                k[NET[e][0]] = min(x, y);
-                k[NET[e][1]] = max(x, y);
-            }
-#pragma unroll
-            for (int q = 0; q < PUSH_PPT; ++q) visit |= (k[q] & 7u) << (3 * q);
+            for (int q = 0; q < PPT; ++q) visit |= (Visit)(k[q] & ((1u << VB) - 1u)) << (VB * q);
         }
         // window [lo, hi] of cells this wavefront's deposit can touch: in a tile in
         // position order, the first lane's lowest and the last lane's highest cell;
@@ -769,8 +802,8 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
             }
         };
 #pragma unroll 1
-        for (int q = 0; q < PUSH_PPT; ++q) {
-            const int slot = (visit >> (3 * q)) & 7;
+        for (int q = 0; q < PPT; ++q) {
+            const int slot = (int)(visit >> (VB * q)) & ((1 << VB) - 1);
             const int c0 = sPc[wid][slot][lane];
             const bool alive = c0 != DEAD_CELL;
             if (alive && c0 != cc.cell) {
@@ -818,12 +851,12 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
         flush_run(3);
         // write back (vector stores for full groups; never touch slots >= ncur, where
         // appended particles may be landing)
-        if (nv == PUSH_PPT) {
+        if (nv == PPT) {
             int4* cp = reinterpret_cast<int4*>(a.cell + base + ib);
             float4* op = reinterpret_cast<float4*>(a.off + base + ib);
             float4* up = reinterpret_cast<float4*>(a.u + base + ib);
 #pragma unroll
-            for (int h = 0; h < PUSH_PPT / 4; ++h) {
+            for (int h = 0; h < PPT / 4; ++h) {
                 cp[h] = make_int4(sPc[wid][4 * h][lane], sPc[wid][4 * h + 1][lane], sPc[wid][4 * h + 2][lane],
                                   sPc[wid][4 * h + 3][lane]);
                 op[h] = make_float4(sPo[wid][4 * h][lane], sPo[wid][4 * h + 1][lane], sPo[wid][4 * h + 2][lane],
@@ -833,7 +866,7 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < PUSH_PPT; ++q) {
+            for (int q = 0; q < PPT; ++q) {
                 if (q < nv) {
                     a.cell[base + ib + q] = sPc[wid][q][lane];
                     a.off[base + ib + q] = sPo[wid][q][lane];
@@ -855,10 +888,21 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
     if (cur_line >= 0) counts_flush(a.counters, cur_line, cnt);
 }
 
-template __global__ void k_push<RICS_OFF>(PushArgs);
-template __global__ void k_push<RICS_EXACT>(PushArgs);
-template __global__ void k_push<RICS_TABLE>(PushArgs);
-template __global__ void k_push<RICS_MLP>(PushArgs);
+// the shapes the autotuner chooses from: 4, 8 or 16 particles per lane, and two
+// deposit windows per backend
+template __global__ void k_push<RICS_OFF, 4, 32>(PushArgs);
+template __global__ void k_push<RICS_OFF, 8, 32>(PushArgs);
+template __global__ void k_push<RICS_OFF, 16, 32>(PushArgs);
+template __global__ void k_push<RICS_OFF, 8, 64>(PushArgs);
+template __global__ void k_push<RICS_EXACT, 4, 32>(PushArgs);
+template __global__ void k_push<RICS_EXACT, 8, 32>(PushArgs);
+template __global__ void k_push<RICS_EXACT, 16, 32>(PushArgs);
+template __global__ void k_push<RICS_EXACT, 8, 64>(PushArgs);
+template __global__ void k_push<RICS_TABLE, 4, 128>(PushArgs);
+template __global__ void k_push<RICS_TABLE, 8, 128>(PushArgs);
+template __global__ void k_push<RICS_TABLE, 16, 128>(PushArgs);
+template __global__ void k_push<RICS_TABLE, 8, 64>(PushArgs);
+template __global__ void k_push<RICS_MLP, 8, 32>(PushArgs);
 
 // ---------------------------------------------------------------------------
 // Photon conversion (Sec. 3): every recorded photon with E >= 2 m_e c^2 turns into
@@ -1142,7 +1186,7 @@ __device__ void bookkeeping(const BookArgs& b) {
         const int n = min(b.alloc[s], b.seg_cap[s]);
         b.n_cur[s] = n;
         b.alloc[s] = n;
-        sum += (n + PUSH_TILE - 1) / PUSH_TILE;
+        sum += (n + b.tile - 1) / b.tile;
     }
     sPart[threadIdx.x] = sum;
     __syncthreads();
@@ -1155,7 +1199,7 @@ __device__ void bookkeeping(const BookArgs& b) {
     int run = sPart[threadIdx.x] - sum;     // exclusive prefix
     for (int s = s0; s < min(s0 + per, nseg); ++s) {
         b.tile_prefix[s] = run;
-        run += (b.n_cur[s] + PUSH_TILE - 1) / PUSH_TILE;
+        run += (b.n_cur[s] + b.tile - 1) / b.tile;
     }
     if (threadIdx.x == 255) b.tile_prefix[nseg] = sPart[255];
 }
@@ -1634,8 +1678,8 @@ __global__ __launch_bounds__(256) void k_sort_count(SortArgs s) {
         const LineDev& L = s.lines[seg >> 2];
         const int ncur = s.n_cur[seg];
         const int64_t base = s.seg_base[seg];
-        const int i0 = (t - s.tile_prefix[seg]) * PUSH_TILE;
-        for (int q = 0; q < AUX_PPT; ++q) {
+        const int i0 = (t - s.tile_prefix[seg]) * s.tile;
+        for (int q = 0; q < s.tile / PUSH_TPB; ++q) {
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
             const int c = (i < ncur) ? s.cell[base + i] : DEAD_CELL;
             const bool live = c != DEAD_CELL;
@@ -1744,8 +1788,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs s) {
         const int ncur = s.n_cur[seg];
         const int cap = s.seg_cap[seg];
         const int64_t base = s.seg_base[seg];
-        const int i0 = (t - s.tile_prefix[seg]) * PUSH_TILE;
-        for (int q = 0; q < AUX_PPT; ++q) {
+        const int i0 = (t - s.tile_prefix[seg]) * s.tile;
+        for (int q = 0; q < s.tile / PUSH_TPB; ++q) {
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
             const int c = (i < ncur) ? s.cell[base + i] : DEAD_CELL;
             const bool live = c != DEAD_CELL;
@@ -1811,6 +1855,28 @@ __global__ __launch_bounds__(256) void k_init_pairs(InitArgs a) {
     a.cell[kp] = cell; a.off[kp] = off; a.u[kp] = up; a.id[kp] = a.id_base + 2 * (uint64_t)i + 1;
 }
 
+// Sum of v over the run of consecutive lanes that share this lane's key, in the
+// run's first lane (head = true there).  Every lane of the wavefront must take part.
+// Keys need not be sorted: equal keys that are not adjacent form runs of their own.
+__device__ __forceinline__ long long wave_run_sum(int key, long long v, bool& head) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1, 64);
+    const int next = __shfl_down(key, 1, 64);
+    head = lane == 0 || prev != key;
+    const bool tail = lane == 63 || next != key;
+    long long p = v;                                  // inclusive prefix sum
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(p, o, 64);
+        if (lane >= o) p += y;
+    }
+    const unsigned long long T = __ballot(tail);      // bit 63 always set
+    const int e = lane + __builtin_ctzll(T >> lane);  // the run's last lane
+    const long long pe = __shfl(p, e, 64);
+    const long long pb = __shfl(p, lane > 0 ? lane - 1 : 0, 64);
+    return pe - (lane > 0 ? pb : 0ll);
+}
+
 // Histogram of live particles per cell and species (after init / set_particles).
 __global__ __launch_bounds__(256) void k_hist(HistArgs h) {
     const int total = h.tile_prefix[h.nseg];
@@ -1821,12 +1887,14 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs h) {
         const LineDev& L = h.lines[seg >> 2];
         const int ncur = h.n_cur[seg];
         const int64_t base = h.seg_base[seg];
-        const int i0 = (t - h.tile_prefix[seg]) * PUSH_TILE;
-        for (int q = 0; q < AUX_PPT; ++q) {
+        const int i0 = (t - h.tile_prefix[seg]) * h.tile;
+        for (int q = 0; q < h.tile / PUSH_TPB; ++q) {
+            // one atomic per run of lanes in the same cell (every lane takes part)
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
-            if (i >= ncur) continue;
-            const int c = h.cell[base + i];
-            if (c != DEAD_CELL) atomicAdd(&h.hist[4 * (size_t)(L.cell_base + c) + sp], 1);
+            const int c = i < ncur ? h.cell[base + i] : DEAD_CELL;
+            bool head;
+            const long long n = wave_run_sum(c == DEAD_CELL ? -1 : c, c == DEAD_CELL ? 0 : 1, head);
+            if (head && c != DEAD_CELL) atomicAdd(&h.hist[4 * (size_t)(L.cell_base + c) + sp], (int)n);
         }
     }
 }
@@ -1848,20 +1916,28 @@ __global__ __launch_bounds__(256) void k_moments_particles(MomArgs m) {
         const int sp = seg & 3;
         const int ncur = m.n_cur[seg];
         const int64_t base = m.seg_base[seg];
-        const int i0 = (t - m.tile_prefix[seg]) * PUSH_TILE;
+        const int i0 = (t - m.tile_prefix[seg]) * m.tile;
         const double qs = m.sign[sp] * FIX_SCALE;
         const double mass = (sp == 3) ? m.mass_ratio : 1.0;
-        for (int q = 0; q < AUX_PPT; ++q) {
+        for (int q = 0; q < m.tile / PUSH_TPB; ++q) {
+            // every lane takes part in the run sums: absent and dead slots carry key -1
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
-            if (i >= ncur) continue;
-            const int c = m.cell[base + i];
-            if (c == DEAD_CELL) continue;
+            const int c0 = i < ncur ? m.cell[base + i] : DEAD_CELL;
+            const bool live = c0 != DEAD_CELL;
+            const int c = live ? c0 : -1;
             // cloud-in-cell weights of the position quantised as in the deposit (2^-28 cell)
-            const long long f = (long long)(int)(m.off[base + i] * POS_SCALE) << POS_TO_FIX;
+            const long long f = live ? (long long)(int)(m.off[base + i] * POS_SCALE) << POS_TO_FIX : 0ll;
             const long long sg = (qs < 0.0) ? -1 : 1;
-            const double u = (double)m.u[base + i];
-            atomicAdd(&m.rho[c], (unsigned long long)(sg * (4294967296ll - f)));
-            atomicAdd(&m.rho[c + 1], (unsigned long long)(sg * f));
+            const double u = live ? (double)m.u[base + i] : 0.0;
+            // the charge of a run of particles in one cell, added by the run's first lane
+            // (same-address atomics from every particle of a cell would serialise)
+            bool head;
+            const long long a0 = wave_run_sum(c, live ? sg * (4294967296ll - f) : 0ll, head);
+            const long long a1 = wave_run_sum(c, sg * f, head);
+            if (head && live) {
+                atomicAdd(&m.rho[c], (unsigned long long)a0);
+                atomicAdd(&m.rho[c + 1], (unsigned long long)a1);
+            }
             // gamma - 1 = u^2 / (gamma + 1), free of cancellation at small u
             const double v = mass * (u * u / (sqrt(fma(u, u, 1.0)) + 1.0));
             const double sv = v * 0x1.0p48;

@@ -72,7 +72,8 @@ KERNELS = ("push", "append", "field", "plan", "sort", "annihilate")
 class CTuneOut(ctypes.Structure):
     _fields_ = [("push_blocks_per_cu", ctypes.c_int32), ("xcd_walk", ctypes.c_int32), ("sort_interval", ctypes.c_int32),
                 ("n_trials", ctypes.c_int32), ("ms_per_step_before", ctypes.c_double),
-                ("ms_per_step_after", ctypes.c_double)]
+                ("ms_per_step_after", ctypes.c_double), ("push_ppt", ctypes.c_int32),
+                ("deposit_window", ctypes.c_int32)]
 
 
 class CMlpTrainConfig(ctypes.Structure):
@@ -121,6 +122,7 @@ _SIGS = {
     "pic1d_profile_read": (ctypes.c_int, [P, ctypes.POINTER(CProfile)]),
     "pic1d_set_graph": (ctypes.c_int, [P, ctypes.c_int32]),
     "pic1d_autotune": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(CTuneOut)]),
+    "pic1d_set_push_shape": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "pic1d_testparticle_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "pic1d_testparticle_sweep": (ctypes.c_int, [ctypes.POINTER(CTpConfig), ctypes.c_int32, P, P, P, ctypes.c_size_t,
                                                 P]),
@@ -337,6 +339,10 @@ class Pic1D:
         out = CTuneOut()
         self._check(self.lib.pic1d_autotune(self.h, int(trial_steps), ctypes.byref(out)))
         return {k: getattr(out, k) for k, _ in CTuneOut._fields_}
+
+    def set_push_shape(self, blocks_per_cu, ppt, window):
+        """Launch shape of the particle kernel: blocks per CU, particles per lane, deposit window (cells)."""
+        self._check(self.lib.pic1d_set_push_shape(self.h, int(blocks_per_cu), int(ppt), int(window)))
 
     def rics_line_info(self, line=0):
         """(surrogate error estimate on the line, whether the line uses its table)."""

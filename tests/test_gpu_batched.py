@@ -105,6 +105,7 @@ def test_autotune_changes_speed_not_results():
     _print("autotune", out)
     assert out["n_trials"] >= 3
     assert out["push_blocks_per_cu"] in (1, 2, 3, 4, 6, 8)
+    assert out["push_ppt"] in (4, 8, 16) and out["deposit_window"] in (32, 64)
     assert out["ms_per_step_after"] <= out["ms_per_step_before"]
     steps = tuned.moments(0)["step"]
     ref.step(steps)
@@ -187,3 +188,34 @@ def test_cfg3_full_size_sampled_lines_and_ledger():
         _print("cfg3 line", li, cfg["lines"][li]["n_cells"], "cells:", rep)
         assert rep["compared"] > 2000
         assert rep["excused"] <= max(3, 1e-3 * rep["compared"])
+
+
+SHAPES = {"exact": [(4, 32), (8, 32), (16, 32), (8, 64)], "table": [(4, 128), (8, 128), (16, 128), (8, 64)]}
+
+
+@pytest.mark.parametrize("rics", ["exact", "table"])
+def test_every_push_shape_gives_the_same_results(rics):
+    """Every tile shape the autotuner can pick (4, 8 or 16 particles per lane, both
+    deposit windows, several block counts), set at the start and changed between
+    steps (which re-plans the tiles of the live particles), gives the same
+    particles, field and counters as the default shape, bit for bit."""
+    cfg = _ragged(seed=11, rics=rics)
+    ref = Pic1D(cfg)
+    ref.step(7)
+    want = _state(ref)
+    ref.close()
+    shapes = SHAPES[rics]
+    for k, (ppt, ww) in enumerate(shapes):
+        sim = Pic1D(cfg)
+        sim.set_push_shape(1 + k, ppt, ww)
+        sim.step(3)
+        nxt = shapes[(k + 1) % len(shapes)]
+        sim.set_push_shape(2, nxt[0], nxt[1])
+        sim.step(4)
+        _print(rics, "shape", (ppt, ww), "then", nxt)
+        _assert_same(want, _state(sim))
+        sim.close()
+    sim = Pic1D(cfg)
+    with pytest.raises(RuntimeError):
+        sim.set_push_shape(4, 8, 48)
+    sim.close()
