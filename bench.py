@@ -349,7 +349,14 @@ def surrogate_comparison(steps, warmup, mlp_steps):
             eF = np.abs(Fm - Fe)[sig] / np.abs(Fe)[sig]
             sigN = Ne * h > 1e-9
             eN = np.abs(Nm - Ne)[sigN] / Ne[sigN]
+            # the drag half's branch (damping where |F| tau_min > |u|) taken from the network
+            # and from the exact force at the same momenta: tau_min = eta_min (n_psi)^(1/2) / w_p
+            # steps (Sec. 3), w_p = C / d0 per step, one step = h in R*/c
+            cfl = cfg.get("cfl", 0.5)
+            tau_hat = cfg.get("eta_min", 1.0e3) * abs(cfg["j_twist"]) ** 0.5 / (cfl / cfg.get("d0_cells", 48.0)) * h
+            flip = (np.abs(Fm) * tau_hat > uu) != (np.abs(Fe) * tau_hat > uu)
             entry["error_vs_exact"] = {
+                "limiter_branch_flip_rate": float(flip.mean()),
                 "F_median": float(np.median(eF)), "F_p99": float(np.quantile(eF, 0.99)), "F_max": float(eF.max()),
                 "Ndot_median": float(np.median(eN)) if eN.size else None,
                 "Ndot_p99": float(np.quantile(eN, 0.99)) if eN.size else None,

@@ -57,7 +57,7 @@ struct LineDev {
                           //    MLP backend where the network's error estimate exceeds the tolerance)
     int32_t pad_ut;
     float lgk;            // table: (nlg - 1)/16 log10(2): fractional column per unit log2 gamma^2
-    float lgk_hi, lgk_lo; // lgk split into a 10-fraction-bit head and the rest
+    float pad_lgk[2];
     float s_scale_f;      // table: s_scale in float32 (rows per cell)
     double s_scale;       // table: ns / n_cells
     double lg_scale;      // table: (nlg - 1) / 8

@@ -154,13 +154,7 @@ void build_line(const pic1d_config* c, int line, int32_t cell_base, int32_t tabl
     d.lg_scale = table ? (c->table_nlg - 1) / 8.0 : 0.0;
     d.use_table = c->rics_backend == 2 ? 1 : 0;     // the MLP backend's lines decide at init
     d.s_scale_f = (float)d.s_scale;
-    {
-        const double k = 0.5 * d.lg_scale * log10(2.0);
-        const double k_hi = floor(k * 1024.0) / 1024.0;
-        d.lgk = (float)k;
-        d.lgk_hi = (float)k_hi;
-        d.lgk_lo = (float)(k - k_hi);
-    }
+    d.lgk = (float)(0.5 * d.lg_scale * log10(2.0));
     const double nmax = (c->nmax_over_n0 > 0.0 ? c->nmax_over_n0 : c->d0_cells * c->d0_cells) * c->ppc0;
     d.nmax = (float)nmax;
     d.half_n = 0.5f * (float)n;

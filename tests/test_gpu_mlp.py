@@ -362,3 +362,44 @@ def test_mixed_step_parity_with_table_fallback():
     for li in range(len(radii)):
         assert sim.moments(li)["gauss_residual"] <= 1e-6
     sim.close()
+
+
+def test_precision_ablation_of_the_trained_network():
+    """Which precision sets the trained surrogate's error floor.  The network is trained
+    on the GPU (float32 master weights; the forward pass with bfloat16 weights and
+    three-term bfloat16 activations), then the force factor 10^o1 = |F|/|gamma mu - u|
+    and the rate 10^o2 are scored against the exact targets on held-out samples for
+      (a) the GPU forward,
+      (b) the FP64 oracle forward with the same bfloat16-rounded weights,
+      (c) the FP64 oracle forward with the float32 master weights (no rounding).
+    (a) matches (b) to the forward's tolerance.  (c) against (b) is the ablation: the
+    error the bfloat16 weights add on top of the fit."""
+    import torch
+    r = pic1d.mlp_train(seed=5, n_samples=1 << 20, batch=8192, steps=20000, lr=2e-3, lr_final=2e-6, n_loss=5)
+    X, O, _ = omlp.training_samples(seed=5, n=20000, first=1 << 41)
+    P = r["params"].astype(np.float64)
+    mean = r["norm"][:3].astype(np.float64)
+    std = r["norm"][3:].astype(np.float64)
+    out_a = pic1d.mlp_forward(torch.from_numpy(r["params"]).cuda(), torch.from_numpy(X).cuda()).cpu().numpy()
+    Xn = omlp.normalize_inputs(X.astype(np.float64))
+    out_b = omlp.forward(P, Xn, round_weights=True)[0]
+    out_c = omlp.forward(P, Xn, round_weights=False)[0]
+
+    def rel(out):
+        o = out.astype(np.float64) * std + mean
+        return np.abs(10.0 ** (o - O) - 1.0)
+    res = {}
+    for name, out in (("a GPU bf16", out_a), ("b FP64, bf16 weights", out_b), ("c FP64, fp32 weights", out_c)):
+        e = rel(out)
+        res[name] = e
+        _print(f"{name}: F factor median {np.median(e[:, 0]):.3e} p99 {np.quantile(e[:, 0], 0.99):.3e} "
+               f"max {e[:, 0].max():.3e}; Ndot median {np.median(e[:, 1]):.3e} p99 {np.quantile(e[:, 1], 0.99):.3e} "
+               f"max {e[:, 1].max():.3e}")
+    ea, eb, ec = res["a GPU bf16"], res["b FP64, bf16 weights"], res["c FP64, fp32 weights"]
+    # (a) and (b): the same network to the forward's tolerance (relative ln(10) std OUT_TOL)
+    for k in (0, 1):
+        assert np.max(np.abs(ea[:, k] - eb[:, k]) / (1.0 + eb[:, k])) <= 10 * np.log(10) * std[k] * OUT_TOL
+    # the bfloat16 weights move the outputs by about their 2^-9 relative rounding; the
+    # fit's own error sits on top of that either way
+    _print("median ratio bf16 / fp32 weights:", np.median(eb[:, 0]) / np.median(ec[:, 0]),
+           np.median(eb[:, 1]) / np.median(ec[:, 1]))
