@@ -106,6 +106,8 @@ struct pic1d_state {
     int push_bpc = 0;                              // push blocks per CU
     int ppt = PUSH_PPT_DEFAULT;                    // particles per lane per tile of the push
     int ww = 0;                                    // deposit window of the push (cells)
+    int n_table_lines = 0;                         // MLP with table fallback: lines on their table
+    int push_blocks_table = 0;                     // ... and the table kernel's blocks for them
     int graph_steps = 0;                           // requested steps per graph; 0 = eager
     int graph_len = 0;                             // steps per graph (a multiple of sort_interval)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // by the live buffer set at the graph's start
@@ -253,19 +255,19 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
 const void* push_kernel(int backend, int ppt, int ww) {
     switch (backend) {
         case RICS_OFF:
-            if (ww == 32) return ppt == 4 ? (const void*)k_push<RICS_OFF, 4, 32> : ppt == 8 ? (const void*)k_push<RICS_OFF, 8, 32>
-                               : ppt == 16 ? (const void*)k_push<RICS_OFF, 16, 32> : nullptr;
-            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_OFF, 8, 64> : nullptr;
+            if (ww == 32) return ppt == 4 ? (const void*)k_push<RICS_OFF, 4, 32, 0> : ppt == 8 ? (const void*)k_push<RICS_OFF, 8, 32, 0>
+                               : ppt == 16 ? (const void*)k_push<RICS_OFF, 16, 32, 0> : nullptr;
+            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_OFF, 8, 64, 0> : nullptr;
         case RICS_EXACT:
-            if (ww == 32) return ppt == 4 ? (const void*)k_push<RICS_EXACT, 4, 32> : ppt == 8 ? (const void*)k_push<RICS_EXACT, 8, 32>
-                               : ppt == 16 ? (const void*)k_push<RICS_EXACT, 16, 32> : nullptr;
-            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_EXACT, 8, 64> : nullptr;
+            if (ww == 32) return ppt == 4 ? (const void*)k_push<RICS_EXACT, 4, 32, 0> : ppt == 8 ? (const void*)k_push<RICS_EXACT, 8, 32, 0>
+                               : ppt == 16 ? (const void*)k_push<RICS_EXACT, 16, 32, 0> : nullptr;
+            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_EXACT, 8, 64, 0> : nullptr;
         case RICS_TABLE:
-            if (ww == 128) return ppt == 4 ? (const void*)k_push<RICS_TABLE, 4, 128> : ppt == 8 ? (const void*)k_push<RICS_TABLE, 8, 128>
-                                : ppt == 16 ? (const void*)k_push<RICS_TABLE, 16, 128> : nullptr;
-            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_TABLE, 8, 64> : nullptr;
+            if (ww == 128) return ppt == 4 ? (const void*)k_push<RICS_TABLE, 4, 128, 0> : ppt == 8 ? (const void*)k_push<RICS_TABLE, 8, 128, 0>
+                                : ppt == 16 ? (const void*)k_push<RICS_TABLE, 16, 128, 0> : nullptr;
+            return (ww == 64 && ppt == 8) ? (const void*)k_push<RICS_TABLE, 8, 64, 0> : nullptr;
         case RICS_MLP:
-            return (ww == 32 && ppt == 8) ? (const void*)k_push<RICS_MLP, 8, 32> : nullptr;
+            return (ww == 32 && ppt == 8) ? (const void*)k_push<RICS_MLP, 8, 32, 0> : nullptr;
         default:
             return nullptr;
     }
@@ -338,12 +340,25 @@ void prof_collect(pic1d_state* st) {
 
 int launch_push(pic1d_state* st) {
     PushArgs a = push_args(st);
-    const void* kp = push_kernel(st->backend, st->ppt, st->ww);
-    if (!kp) return fail(st, PIC1D_EINVAL, "push shape not built");
     void* args[] = {&a};
     const int pk = prof_begin(st, 0);
-    HIP_TRY(st, hipLaunchKernel(kp, dim3(st->push_blocks), dim3(st->backend == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB),
-                                args, 0, st->stream));
+    if (st->backend == RICS_MLP && st->n_table_lines > 0) {
+        // the surrogate with table fallback: the lines on their tables through the table
+        // kernel (its own occupancy; the MLP kernel holds one wavefront per SIMD), the
+        // lines on the network through the MLP kernel
+        const int n_net = st->lay.n_lines - st->n_table_lines;
+        if (st->ppt != 8 || st->ww != 32) return fail(st, PIC1D_EINVAL, "push shape not built");
+        const void* kt = n_net > 0 ? (const void*)k_push<RICS_TABLE, 8, 128, 1> : (const void*)k_push<RICS_TABLE, 8, 128, 0>;
+        HIP_TRY(st, hipLaunchKernel(kt, dim3(st->push_blocks_table), dim3(PUSH_TPB), args, 0, st->stream));
+        if (n_net > 0)
+            HIP_TRY(st, hipLaunchKernel((const void*)k_push<RICS_MLP, 8, 32, 2>, dim3(st->push_blocks), dim3(PUSH_TPB_MLP),
+                                        args, 0, st->stream));
+    } else {
+        const void* kp = push_kernel(st->backend, st->ppt, st->ww);
+        if (!kp) return fail(st, PIC1D_EINVAL, "push shape not built");
+        HIP_TRY(st, hipLaunchKernel(kp, dim3(st->push_blocks), dim3(st->backend == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB),
+                                    args, 0, st->stream));
+    }
     prof_end(st, pk);
     return PIC1D_OK;
 }
@@ -580,7 +595,12 @@ int pic1d_init(const pic1d_config* cfg, pic1d_state** out) {
                 st->mlp_error[l] = e;
                 ld[l].use_table = (double)e > cfg->mlp_fallback_tol ? 1 : 0;
                 st->lines[l].dev.use_table = ld[l].use_table;
+                st->n_table_lines += ld[l].use_table;
             }
+            int occ_t = 0;
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ_t, push_kernel(RICS_TABLE, st->ppt, default_window(RICS_TABLE)), PUSH_TPB, 0);
+            st->push_blocks_table = st->n_cu * std::max(1, std::min(occ_t, 8));
             INIT_TRY(hipMemcpyAsync(st->dlines, ld.data(), ld.size() * sizeof(LineDev), hipMemcpyHostToDevice, s));
         }
     }

@@ -266,7 +266,8 @@ void gauss_legendre(int n, double* x, double* w);
 hipError_t launch_disk_table(const DiskTableArgs& a, hipStream_t s);
 constexpr int DISK_N_C = 24, DISK_N_PHI = 24;
 
-template <int BACKEND, int PPT, int WW> __global__ void k_push(PushArgs a);
+// KIND: 0 every line; 1 only the lines on their table; 2 only the lines on the network
+template <int BACKEND, int PPT, int WW, int KIND> __global__ void k_push(PushArgs a);
 __global__ void k_mlp_pack(const float* p, bf16x8* ft, bf16x8* bt, float* bias);
 // The surrogate's error estimate on every line: the largest relative error of
 // F_hat and Ndot_hat against the float64 closed forms over the line's table nodes,

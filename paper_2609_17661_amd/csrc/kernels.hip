@@ -597,7 +597,7 @@ __device__ __forceinline__ void wave_sync() {
 // merges its lanes in a private LDS window and flushes the window to the global
 // fixed-point current with one atomic per touched cell.  No block-level
 // synchronisation.
-template <int BACKEND, int PPT, int WW>
+template <int BACKEND, int PPT, int WW, int KIND>
 __global__ __launch_bounds__(BACKEND == RICS_MLP ? PUSH_TPB_MLP : PUSH_TPB)
 __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a) {
     static_assert(PPT == 4 || PPT == 8 || PPT == 16, "4, 8 or 16 particles per lane");
@@ -675,6 +675,15 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
             cur_line = line;
         }
         const LineDev L = kconst(a.lines)[line];
+        // the surrogate's states with lines on both sources push them in two launches
+        // (table lines at the table kernel's occupancy): a tile of the other kind is
+        // left to the other launch
+        if constexpr (KIND != 0) {
+            if ((L.use_table != 0) != (KIND == 1)) {
+                fetch(ww.t + ww.stride);
+                continue;
+            }
+        }
         // the fetched particles, staged in the wave's LDS slots [q][lane] so the
         // particle loop indexes them freely without bank conflicts.  Dead slots are
         // stored as (DEAD_CELL, 1/2, 0); the padding of a partial tile is made so.
@@ -711,11 +720,8 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
         // the first cell's cache, loaded early so that its latency hides under the
         // tile set-up below
         const float qmC = ((sp == 0 || sp == 2) ? -1.0f : (sp == 1 ? 1.0f : a.qm_ion)) * L.invC;
-        // the surrogate's lines whose error estimate failed take their table (tile-uniform)
-        const bool tab_line = BACKEND == RICS_MLP && L.use_table != 0;
         CellCache cc;
-        if (tab_line) cache_load<RICS_TABLE>(cc, a, L, qmC, first);
-        else cache_load<BACKEND>(cc, a, L, qmC, first);
+        cache_load<BACKEND>(cc, a, L, qmC, first);
         // The order in which the lane visits its slots: by cell (dead slots last), so
         // that the run accumulator and the cell cache see each cell once however the
         // particles of a cell are ordered in memory.  A sorting network on keys
@@ -818,8 +824,7 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
                     flush_run(3);
                     jv0 = jv1 = jv2 = hc = 0;
                 }
-                if (tab_line) cache_load<RICS_TABLE>(cc, a, L, qmC, c0);
-                else cache_load<BACKEND>(cc, a, L, qmC, c0);
+                cache_load<BACKEND>(cc, a, L, qmC, c0);
                 key = c0;
             }
             float uq = sPu[wid][slot][lane];
@@ -827,17 +832,8 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
             int c1, d, jm, j0, jp;
             float o1;
             bool gone;
-            if constexpr (BACKEND == RICS_MLP) {
-                if (tab_line)
-                    advance_particle<RICS_TABLE>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt,
-                                                 c1, o1, jm, j0, jp, d, gone, sW, sWb);
-                else
-                    advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1,
-                                              o1, jm, j0, jp, d, gone, sW, sWb);
-            } else {
-                advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1,
-                                          o1, jm, j0, jp, d, gone, sW, sWb);
-            }
+            advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1, o1,
+                                      jm, j0, jp, d, gone, sW, sWb);
             cnt.pushed += alive ? 1 : 0;
             cnt.pushed_ion += (alive && sp == 3) ? 1 : 0;
             jv0 += jm;
@@ -890,19 +886,23 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
 
 // the shapes the autotuner chooses from: 4, 8 or 16 particles per lane, and two
 // deposit windows per backend
-template __global__ void k_push<RICS_OFF, 4, 32>(PushArgs);
-template __global__ void k_push<RICS_OFF, 8, 32>(PushArgs);
-template __global__ void k_push<RICS_OFF, 16, 32>(PushArgs);
-template __global__ void k_push<RICS_OFF, 8, 64>(PushArgs);
-template __global__ void k_push<RICS_EXACT, 4, 32>(PushArgs);
-template __global__ void k_push<RICS_EXACT, 8, 32>(PushArgs);
-template __global__ void k_push<RICS_EXACT, 16, 32>(PushArgs);
-template __global__ void k_push<RICS_EXACT, 8, 64>(PushArgs);
-template __global__ void k_push<RICS_TABLE, 4, 128>(PushArgs);
-template __global__ void k_push<RICS_TABLE, 8, 128>(PushArgs);
-template __global__ void k_push<RICS_TABLE, 16, 128>(PushArgs);
-template __global__ void k_push<RICS_TABLE, 8, 64>(PushArgs);
-template __global__ void k_push<RICS_MLP, 8, 32>(PushArgs);
+template __global__ void k_push<RICS_OFF, 4, 32, 0>(PushArgs);
+template __global__ void k_push<RICS_OFF, 8, 32, 0>(PushArgs);
+template __global__ void k_push<RICS_OFF, 16, 32, 0>(PushArgs);
+template __global__ void k_push<RICS_OFF, 8, 64, 0>(PushArgs);
+template __global__ void k_push<RICS_EXACT, 4, 32, 0>(PushArgs);
+template __global__ void k_push<RICS_EXACT, 8, 32, 0>(PushArgs);
+template __global__ void k_push<RICS_EXACT, 16, 32, 0>(PushArgs);
+template __global__ void k_push<RICS_EXACT, 8, 64, 0>(PushArgs);
+template __global__ void k_push<RICS_TABLE, 4, 128, 0>(PushArgs);
+template __global__ void k_push<RICS_TABLE, 8, 128, 0>(PushArgs);
+template __global__ void k_push<RICS_TABLE, 16, 128, 0>(PushArgs);
+template __global__ void k_push<RICS_TABLE, 8, 64, 0>(PushArgs);
+template __global__ void k_push<RICS_MLP, 8, 32, 0>(PushArgs);
+// the surrogate's states with lines on both sources: the table lines alone, the
+// network lines alone
+template __global__ void k_push<RICS_TABLE, 8, 128, 1>(PushArgs);
+template __global__ void k_push<RICS_MLP, 8, 32, 2>(PushArgs);
 
 // ---------------------------------------------------------------------------
 // Photon conversion (Sec. 3): every recorded photon with E >= 2 m_e c^2 turns into
