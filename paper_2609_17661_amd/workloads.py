@@ -75,13 +75,13 @@ def cfg3(n_lines=256, seed=0, rics="table", headroom=1.05):
                 pairs=True, conversion="curvature", seed=seed, sort_interval=50, lines=lines)
 
 
-def cfg5(n_lines=64, seed=0, rics="table", n_cells=32768, ppc=64, nmax_over_n0=8.5, ppc0=32.0):
+def cfg5(n_lines=64, seed=0, rics="table", n_cells=32768, ppc=84, nmax_over_n0=11.0, ppc0=32.0):
     """The combined cascade run: 64 lines with R_max log-uniform in [10, 100], 32,768
     cells each, a hot pair seed (gamma log-uniform to 1e4) cascading up to
     n_max = nmax_over_n0 * ppc0 particles per cell, the surface atmosphere with ions
-    at m_i/m_e = 100, pairs with curvature conversion.  The cascade settles at about
-    70% of n_max averaged over the lines (the footpoint regions stay below it), so
-    n_max = 8.5 n0 holds about 4e8 particles over 64 lines."""
+    at m_i/m_e = 100, pairs with curvature conversion.  The resident count levels
+    off where pair creation and annihilation over n_max balance; with a seed of 84
+    pairs per cell and n_max = 11 n0 that is about 4e8 particles over 64 lines."""
     rng = np.random.default_rng(seed)
     R = 10.0 * 10.0 ** rng.random(n_lines)
     nmax = nmax_over_n0 * ppc0
