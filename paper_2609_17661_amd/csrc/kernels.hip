@@ -497,8 +497,7 @@ __device__ __forceinline__ void advance_particle(const PushArgs& a, const LineDe
     } else {
         u += kick;
     }
-    u = alive ? u : 0.0f;
-    if (!isfinite(u)) set_error(&a.sc->err, -5);
+    u = alive ? u : 0.0f;      // (a non-finite u is reported once per tile by the caller)
 
     // move x^{n+1} = x^n + C u / gamma with the offset carried into the cell index
     // (|C u / gamma| < 1/2, so the carry is -1, 0 or 1 and o1 - carry is exact; o1 + 1
@@ -807,6 +806,7 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
                 }
             }
         };
+        bool nonfinite = false;
 #pragma unroll 1
         for (int q = 0; q < PPT; ++q) {
             const int slot = (int)(visit >> (VB * q)) & ((1 << VB) - 1);
@@ -834,6 +834,7 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
             bool gone;
             advance_particle<BACKEND>(a, L, T, cc, alive, line, sp, base + ib + slot, cc.cell, oq, uq, cnt, c1, o1,
                                       jm, j0, jp, d, gone, sW, sWb);
+            nonfinite = nonfinite || !isfinite(uq);
             cnt.pushed += alive ? 1 : 0;
             cnt.pushed_ion += (alive && sp == 3) ? 1 : 0;
             jv0 += jm;
@@ -845,6 +846,7 @@ __attribute__((amdgpu_waves_per_eu(push_waves(BACKEND)))) void k_push(PushArgs a
             sPu[wid][slot][lane] = gone ? 0.0f : uq;
         }
         flush_run(3);
+        if (nonfinite) set_error(&a.sc->err, -5);
         // write back (vector stores for full groups; never touch slots >= ncur, where
         // appended particles may be landing)
         if (nv == PPT) {
