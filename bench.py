@@ -29,7 +29,7 @@ geometry at the same particle count (65,536 cells x 200 hot e-/e+ per cell) is
 stepped with the TABLE, EXACT and MLP backends in turn.  The network's error is
 judged against the library's EXACT backend at the workload's particles.
 
-Cascade run (`--cascade`, not part of the default line): 64 lines of 32,768
+Cascade run (`cascade`; `--cascade` runs it alone): 64 lines of 32,768
 cells whose hot pair seed cascades up to n_max (about 4e8 particles), stepped
 from 100-step graphs in chunks; wall time, particle count and pair multiplicity
 per chunk, and k_push's HBM rate at the final count.  The RICS source is the
@@ -542,6 +542,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cascade", action="store_true", help="skip the combined cascade run (cfg5) leg")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate comparison (for profiling its kernels)")
     ap.add_argument("--surrogate-steps", type=int, default=10)
@@ -630,6 +631,9 @@ def main():
         res["batched"] = batched_path(100, 5)
     if not args.no_surrogate:
         res["surrogate_vs_table"] = surrogate_comparison(args.surrogate_steps, 30, args.mlp_train_steps)
+    if not args.no_cascade:
+        res["cascade"] = cascade_run(args.cascade_chunks, 100, 20, args.cascade_mlp_train_steps)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(res), flush=True)

@@ -29,7 +29,9 @@ inline int fail(void*, int code, const std::string& msg) { return set_global_err
 constexpr uint32_t STREAM_MLP_SAMPLE = 7, STREAM_MLP_INIT = 8, STREAM_MLP_BATCH = 9;
 constexpr int MLP_MAX_ATTEMPTS = 64;
 constexpr int MLP_CHUNK = 256;          // samples per weight-gradient block
+constexpr int WGRAD_ZSPLIT = 4;         // blocks sharing one chunk of a 128 x 128 layer's tiles
 constexpr int MLP_TPB = 256;
+constexpr int ADAM_BLOCKS = (MLP_NPARAM + MLP_TPB - 1) / MLP_TPB;   // one parameter per thread
 
 // float64 constants of the RICS prefactors (CODATA 2018; R* = 1e6 cm)
 constexpr double kMlpRe = 2.8179403262e-13, kMlpLbar = 3.8615926796e-11, kMlpMeC2 = 510.99895, kMlpRstar = 1.0e6;
@@ -349,6 +351,11 @@ __global__ __launch_bounds__(MLP_TPB) void k_mlp_wgrad(const float4* __restrict_
                    : layer == 4 ? MLP_OFF_W4 : MLP_OFF_W5;
     const int offB = offW + M * N;
     const int nTo = (M + 15) / 16, nTi = (N + 15) / 16, ntile = nTo * nTi;
+    // the 128 x 128 layers split their 64 tiles over the blocks of gridDim.z (more
+    // blocks than CUs at training batches); the small layers take z = 0 alone
+    const int zsplit = (M == MLP_W && N == MLP_W) ? (int)gridDim.z : 1;
+    if ((int)blockIdx.z >= zsplit) return;
+    const int t_first = (int)blockIdx.z * (ntile / zsplit), t_end = t_first + ntile / zsplit;
     const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
     const int w = threadIdx.x >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * MLP_CHUNK;
@@ -363,7 +370,10 @@ __global__ __launch_bounds__(MLP_TPB) void k_mlp_wgrad(const float4* __restrict_
             const int s = e / MLP_W, c = e % MLP_W;
             const int64_t row = s0 + s;
             float dv = 0.0f, av = 0.0f;
-            if (c < M) {
+            // the deltas of the block's output rows (all rows in block z = 0, which also
+            // sums the bias gradient)
+            const bool dneed = blockIdx.z == 0 || (c >= 32 * (int)blockIdx.z && c < 32 * (int)blockIdx.z + 32);
+            if (c < M && dneed) {
                 if (layer == 5) {
                     const float4 v = DOUT[row];
                     dv = c == 0 ? v.x : c == 1 ? v.y : v.z;
@@ -383,15 +393,15 @@ __global__ __launch_bounds__(MLP_TPB) void k_mlp_wgrad(const float4* __restrict_
             sA[c][s] = av;
         }
         __syncthreads();
-        if ((int)threadIdx.x < M) {
+        if (blockIdx.z == 0 && (int)threadIdx.x < M) {
             float s = 0.0f;
             for (int k = 0; k < 32; ++k) s += sD[threadIdx.x][k];
             db += s;
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const int t = w + 4 * k;
-            if (t < ntile) {
+            const int t = t_first + w + 4 * k;
+            if (t < t_end) {
                 const int To = t / nTi, Ti = t % nTi;
                 float dv[8], av[8];
                 const float4 d0 = *reinterpret_cast<const float4*>(&sD[16 * To + r][8 * g]);
@@ -420,8 +430,8 @@ __global__ __launch_bounds__(MLP_TPB) void k_mlp_wgrad(const float4* __restrict_
     float* out = partial + (int64_t)blockIdx.x * MLP_NPARAM;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const int t = w + 4 * k;
-        if (t < ntile) {
+        const int t = t_first + w + 4 * k;
+        if (t < t_end) {
             const int To = t / nTi, Ti = t % nTi;
             const int i = 16 * Ti + r;
 #pragma unroll
@@ -431,7 +441,7 @@ __global__ __launch_bounds__(MLP_TPB) void k_mlp_wgrad(const float4* __restrict_
             }
         }
     }
-    if ((int)threadIdx.x < M) out[offB + threadIdx.x] = db;
+    if (blockIdx.z == 0 && (int)threadIdx.x < M) out[offB + threadIdx.x] = db;
 }
 
 // Sum of the chunk partials (fixed order) and, if apply, one Adam step
@@ -446,6 +456,7 @@ __global__ __launch_bounds__(MLP_TPB) void k_mlp_adam(const float* __restrict__ 
                                                       AdamArgs h) {
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < MLP_NPARAM; e += gridDim.x * blockDim.x) {
         float gsum = 0.0f;
+#pragma unroll 8
         for (int c = 0; c < nchunk; ++c) gsum += partial[(int64_t)c * MLP_NPARAM + e];
         if (grad_out) grad_out[e] = gsum;
         if (apply) {
@@ -570,7 +581,7 @@ int run_grad(const MlpWork& w, TrainFwdArgs fa, hipStream_t s) {
                        s, fa);
     hipLaunchKernelGGL(k_mlp_train_bwd, dim3(std::min<int64_t>(FWD_BLOCKS, (w.rows / 16 + 3) / 4)), dim3(MLP_TPB), 0,
                        s, w.bt, w.DOUT, w.Z, w.DS, (int64_t)(w.rows * MLP_W));
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(w.nchunk, 5), dim3(MLP_TPB), 0, s, w.XN, w.Z, w.DS, w.DOUT,
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(w.nchunk, 5, WGRAD_ZSPLIT), dim3(MLP_TPB), 0, s, w.XN, w.Z, w.DS, w.DOUT,
                        (int64_t)(w.rows * MLP_W), w.partial);
     MLP_TRY(hipGetLastError());
     return PIC1D_OK;
@@ -597,7 +608,7 @@ int loss_grad_on(const MlpWork& w, const float* params, int64_t n, const float* 
     fa.n_batch = n; fa.n_pool = 0; fa.XN = w.XN; fa.Z = w.Z; fa.DOUT = w.DOUT;
     fa.zlayer = w.rows * MLP_W; fa.loss_part = w.loss_part;
     if (int rc = run_grad(w, fa, s)) return rc;
-    hipLaunchKernelGGL(k_mlp_adam, dim3(64), dim3(MLP_TPB), 0, s, w.partial, w.nchunk, nullptr, nullptr, nullptr, grad,
+    hipLaunchKernelGGL(k_mlp_adam, dim3(ADAM_BLOCKS), dim3(MLP_TPB), 0, s, w.partial, w.nchunk, nullptr, nullptr, nullptr, grad,
                        0, adam_args(0.0, 0.0, 0.0, 1.0, 1));
     MLP_TRY(hipGetLastError());
     const double l = sum_loss(w, (int)std::min<int64_t>(FWD_BLOCKS, (w.rows / 16 + 3) / 4), s);
@@ -727,7 +738,7 @@ int pic1d_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t
     if (!params || !m || !v || !grad || t < 1 || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
         return fail(nullptr, PIC1D_EINVAL, "bad arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_mlp_adam, dim3(64), dim3(MLP_TPB), 0, s, grad, 1, params, m, v, nullptr, 1,
+    hipLaunchKernelGGL(k_mlp_adam, dim3(ADAM_BLOCKS), dim3(MLP_TPB), 0, s, grad, 1, params, m, v, nullptr, 1,
                        adam_args(lr, beta1, beta2, eps, t));
     MLP_TRY(hipGetLastError());
     MLP_TRY(hipStreamSynchronize(s));
@@ -802,7 +813,7 @@ int pic1d_mlp_train(const pic1d_mlp_train_config* c, pic1d_mlp_train_result* res
         if (int rc = run_grad(w, fa, s)) return rc;
         const double lr = c->lr_final + 0.5 * (c->lr - c->lr_final) *
                                             (1.0 + std::cos(3.141592653589793 * (double)(t - 1) / (double)c->steps));
-        hipLaunchKernelGGL(k_mlp_adam, dim3(64), dim3(MLP_TPB), 0, s, w.partial, w.nchunk, w.master, w.m, w.v,
+        hipLaunchKernelGGL(k_mlp_adam, dim3(ADAM_BLOCKS), dim3(MLP_TPB), 0, s, w.partial, w.nchunk, w.master, w.m, w.v,
                            nullptr, 1, adam_args(lr, b1, b2, eps, t));
         MLP_TRY(hipGetLastError());
         const bool first = t == 1;
