@@ -59,6 +59,11 @@ independence of the particle order, not by anything the paper fixes.
 The photon energy eps is pinned in tests/test_oracle_rics.py by explicit
 four-momenta (resonant absorption, perpendicular decay, boost back);
 energy conservation through an event pins what the step does with it.
+The angle-resolved events (option 'emission': 'isotropic' or 'dipole' rest-frame
+patterns, the cosine drawn from the second word of the event's Philox block) are
+pinned in tests/test_oracle_emission.py by the printed E_gamma(theta), 60-digit
+Lorentz boosts, the rest-frame mass shell, the paper's bounds on E_gamma and the
+patterns' distribution functions; the patterns themselves are readings.
 """
 import math
 
@@ -81,7 +86,7 @@ DEFAULTS = dict(
     table_ns=512, pairs=False, conversion="immediate", nmax_over_n0=0.0,
     atmosphere=False, atm_a0=0.0, atm_h_cells=0.0, atm_T=0.01, atm_cut=0.01,
     gravity=True, frozen_field=False, seed=0, lines=None, mlp_params=None, mlp_norm=None, mlp_fallback_tol=0.0,
-    annihilation=True, photon_field="radial",
+    annihilation=True, photon_field="radial", emission="perpendicular",
 )
 
 
@@ -196,6 +201,8 @@ class State:
     """Particles and fields of all lines."""
 
     def __init__(self, cfg):
+        if cfg['emission'] not in rics.EMISSION_PATTERNS:
+            raise ValueError(f"emission must be one of {rics.EMISSION_PATTERNS}")
         self.cfg = cfg
         self.lines = []
         base = 0
@@ -422,11 +429,16 @@ def _step_line(st, li, stats):
                 lo, hi = philox.split_id(pid[isr])
                 w = philox.philox4x32_10(nstep, lo, hi, philox.STREAM_RICS, k0, k1)
                 ev = philox.uniform24(w[0]) < p
-                gam = np.sqrt(1.0 + us * us)
-                eps = rics.photon_energy(us, b[isr])
-                gnew = gam - eps
-                dirn = np.where(us >= 0.0, 1.0, -1.0)
-                urec = dirn * np.sqrt(np.maximum(gnew * gnew - 1.0, 0.0))
+                if cfg['emission'] == 'perpendicular':
+                    gam = np.sqrt(1.0 + us * us)
+                    eps = rics.photon_energy(us, b[isr])
+                    gnew = gam - eps
+                    dirn = np.where(us >= 0.0, 1.0, -1.0)
+                    urec = dirn * np.sqrt(np.maximum(gnew * gnew - 1.0, 0.0))
+                else:
+                    # rest-frame emission cosine from the event's second Philox word
+                    mu_r = rics.emission_cosine(philox.uniform24(w[1]), cfg['emission'])
+                    eps, urec, dirn = rics.emission(us, b[isr], mu_r)
                 unew[isr] = np.where(ev, urec, us)
                 if ev.any():
                     cnt['events'] += int(ev.sum())
