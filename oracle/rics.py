@@ -183,7 +183,7 @@ def emission(u, b, mu_r):
     # they cancel: 1 + beta_e mu_r for backward emission, and for forward emission
     # E_e - beta_e E_gamma mu_r = 1 / (E_e + E_gamma mu_r) + E_gamma mu_r (1 - beta_e),
     # the first term from the rest-frame mass shell E_e^2 - (E_gamma mu_r)^2 = 1
-    omb = 1.0 / (ge * ge * (1.0 + be))
+    omb = np.where(ge > 1.0, 1.0 / (ge * ge * (1.0 + be)), 1.0)
     dopp = np.where(mu_r >= 0.0, 1.0 + be * mu_r, be * (1.0 + mu_r) + omb)
     eps = ge * eg * dopp
     g_new = ge * np.where(mu_r >= 0.0, 1.0 / (ee + eg * mu_r) + eg * mu_r * omb, ee - be * eg * mu_r)

@@ -99,6 +99,32 @@ def test_perpendicular_emission_is_the_printed_estimate(b):
 
 
 @pytest.mark.parametrize("b", B_VALUES)
+def test_emission_continuous_in_the_cosine_and_unboosted_below_e_b(b):
+    # the backward and forward forms of the Doppler factors meet at mu_r = 0 for every
+    # gamma; below gamma = E_B (gamma_e < 1, outside the resonance kinematics) the
+    # boost is dropped: eps = gamma_e E_gamma(theta), the lepton recoils against the
+    # photon, and energy is conserved wherever its energy gamma_e E_e reaches m_e
+    q = math.sqrt(1.0 + 2.0 * b)
+    for gam in (0.5 * q, 0.999 * q, q, 1.001 * q, 3.0 * q, 1e5 * q):
+        if gam < 1.0:
+            continue
+        u = np.full(3, math.sqrt(gam * gam - 1.0))
+        eps, un, _ = rics.emission(u, b, np.array([-1e-300, 0.0, 1e-300]))
+        np.testing.assert_allclose(eps, eps[1], rtol=1e-14)
+        # (the lepton's gamma: its momentum near rest is sqrt-sensitive to rounding)
+        np.testing.assert_allclose(np.sqrt(1.0 + un * un), math.sqrt(1.0 + un[1] ** 2), rtol=1e-14)
+        if gam < q:
+            c = np.linspace(-1.0, 1.0, 11)
+            eps, un, dph = rics.emission(np.full(c.shape, u[0]), b, c)
+            np.testing.assert_allclose(eps, gam / q * rics.deexcitation_energy(b, c), rtol=1e-14)
+            np.testing.assert_array_equal(dph, np.where(c >= 0.0, 1.0, -1.0))
+            moving = un != 0.0
+            assert np.all(np.sign(un[moving]) == -np.sign(c[moving]))
+            np.testing.assert_allclose(np.sqrt(1.0 + un[moving] ** 2) + eps[moving], gam, rtol=1e-13)
+            np.testing.assert_array_equal(moving, gam / q * (q - rics.deexcitation_energy(b, c)) > 1.0)
+
+
+@pytest.mark.parametrize("b", B_VALUES)
 def test_emission_between_the_printed_bounds(b):
     # forward emission in the rest frame (mu_r in [0, 1]) gives the lab energies the
     # paper bounds by gamma (1 - m/E_B) and gamma (1 - m^2/E_B^2); along B it reaches
