@@ -60,7 +60,7 @@ The photon energy eps is pinned in tests/test_oracle_rics.py by explicit
 four-momenta (resonant absorption, perpendicular decay, boost back);
 energy conservation through an event pins what the step does with it.
 The angle-resolved events (option 'emission': 'isotropic' or 'dipole' rest-frame
-patterns, the cosine drawn from the second word of the event's Philox block) are
+patterns, the cosine drawn from the other words of the event's Philox block) are
 pinned in tests/test_oracle_emission.py by the printed E_gamma(theta), 60-digit
 Lorentz boosts, the rest-frame mass shell, the paper's bounds on E_gamma and the
 patterns' distribution functions; the patterns themselves are readings.
@@ -436,8 +436,8 @@ def _step_line(st, li, stats):
                     dirn = np.where(us >= 0.0, 1.0, -1.0)
                     urec = dirn * np.sqrt(np.maximum(gnew * gnew - 1.0, 0.0))
                 else:
-                    # rest-frame emission cosine from the event's second Philox word
-                    mu_r = rics.emission_cosine(philox.uniform24(w[1]), cfg['emission'])
+                    # rest-frame emission cosine from the event's other Philox words
+                    mu_r = rics.emission_cosine(w[1], w[2], w[3], cfg['emission'])
                     eps, urec, dirn = rics.emission(us, b[isr], mu_r)
                 unew[isr] = np.where(ev, urec, us)
                 if ev.any():

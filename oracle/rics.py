@@ -135,24 +135,35 @@ def deexcitation_energy(b, c):
 EMISSION_PATTERNS = ("perpendicular", "isotropic", "dipole")
 
 
-def emission_cosine(U, pattern):
-    """Rest-frame emission cosine mu_r (from the excited lepton's motion) for a uniform
-    draw U in [0, 1).  The paper takes the pattern from the two polarisation states of
-    an external reference it does not reproduce; the patterns offered are readings:
+def emission_cosine(w1, w2, w3, pattern):
+    """Rest-frame emission cosine mu_r (from the excited lepton's motion) drawn from the
+    second, third and fourth words of the event's Philox block.  The paper takes the
+    pattern from the two polarisation states of an external reference it does not
+    reproduce; the patterns offered are readings:
       perpendicular  mu_r = 0 (Eq. perpemit, the estimate the paper works with);
-      isotropic      mu_r uniform on [-1, 1]: mu_r = 2U - 1;
+      isotropic      mu_r uniform on [-1, 1]: 2 U1 - 1, U1 from the top 24 bits of w1;
       dipole         density (3/8)(1 + mu_r^2), the classical cyclotron pattern summed
-                     over both polarisations: the inverse of its distribution function
-                     (mu^3 + 3 mu + 4)/8 = U, the root of a depressed cubic with p = 3,
-                     is mu_r = 2 sinh(asinh(4U - 2)/3).
+                     over both polarisations, as the mixture 3/4 uniform on [-1, 1]
+                     (density 3/8) + 1/4 of density (3/8) mu^2 * 4 = (3/2) mu^2, whose
+                     |mu| is the largest of three uniforms (density 3 |mu|^2 on [0, 1])
+                     with a random sign.  The low bits of w1 pick the component (both
+                     of bits 0 and 1 clear: the second, probability 1/4) and bit 2 the
+                     sign; U1, U2, U3 come from the top 24 bits of w1, w2, w3.  Every
+                     draw is exact in binary floating point.
     """
-    U = np.asarray(U, dtype=np.float64)
+    w1 = np.asarray(w1, dtype=np.uint32)
+    u1 = (w1 >> np.uint32(8)).astype(np.float64) * 2.0 ** -24
     if pattern == "perpendicular":
-        return np.zeros_like(U)
+        return np.zeros_like(u1)
     if pattern == "isotropic":
-        return 2.0 * U - 1.0
+        return 2.0 * u1 - 1.0
     if pattern == "dipole":
-        return 2.0 * np.sinh(np.arcsinh(4.0 * U - 2.0) / 3.0)
+        u2 = (np.asarray(w2, dtype=np.uint32) >> np.uint32(8)).astype(np.float64) * 2.0 ** -24
+        u3 = (np.asarray(w3, dtype=np.uint32) >> np.uint32(8)).astype(np.float64) * 2.0 ** -24
+        top = np.maximum(u1, np.maximum(u2, u3))
+        squared = (w1 & np.uint32(3)) == 0
+        sign = np.where((w1 & np.uint32(4)) != 0, -1.0, 1.0)
+        return np.where(squared, sign * top, 2.0 * u1 - 1.0)
     raise ValueError(pattern)
 
 

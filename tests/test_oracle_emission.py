@@ -147,25 +147,43 @@ def test_emission_between_the_printed_bounds(b):
         assert eps[-1] / hi == pytest.approx(1.0, abs=1.0 / ge ** 2)
 
 
+def _cosines(pattern, n=1 << 20):
+    w = philox.philox4x32_10(np.arange(n, dtype=np.uint64), 3, 0, philox.STREAM_RICS, 17, 0)
+    return rics.emission_cosine(w[1], w[2], w[3], pattern), w
+
+
+def _ks(sample, cdf):
+    x = np.sort(sample)
+    n = x.size
+    F = cdf(x)
+    return max(np.max(np.arange(1, n + 1) / n - F), np.max(F - np.arange(n) / n))
+
+
 def test_emission_cosine_patterns():
-    U = (np.arange(200000) + 0.5) / 200000
-    mu = rics.emission_cosine(U, "perpendicular")
+    mu, w = _cosines("perpendicular", 1024)
     assert np.all(mu == 0.0)
-    iso = rics.emission_cosine(U, "isotropic")
-    dip = rics.emission_cosine(U, "dipole")
-    # the draw is the inverse distribution function of each pattern
-    np.testing.assert_allclose((iso + 1.0) / 2.0, U, rtol=0, atol=1e-15)
-    np.testing.assert_allclose((dip ** 3 + 3.0 * dip + 4.0) / 8.0, U, rtol=0, atol=1e-13)
+    iso, w = _cosines("isotropic")
+    dip, _ = _cosines("dipole")
+    np.testing.assert_array_equal(iso, 2.0 * philox.uniform24(w[1]) - 1.0)
+    # every draw is exact in float32, inside [-1, 1]
     for m in (iso, dip):
-        assert np.all(np.diff(m) > 0) and m[0] > -1.0 and m[-1] < 1.0
-    assert float(rics.emission_cosine(0.0, "dipole")) == pytest.approx(-1.0, abs=1e-15)
-    assert float(rics.emission_cosine(0.5, "dipole")) == pytest.approx(0.0, abs=1e-15)
-    # moments of the densities 1/2 and (3/8)(1 + mu^2)
-    assert np.mean(iso ** 2) == pytest.approx(1.0 / 3.0, abs=1e-8)
-    assert np.mean(dip ** 2) == pytest.approx(2.0 / 5.0, abs=1e-8)
-    assert np.mean(dip ** 4) == pytest.approx(9.0 / 35.0, abs=1e-8)
+        assert np.all(m.astype(np.float32).astype(np.float64) == m)
+        assert np.all(np.abs(m) <= 1.0)
+    # Kolmogorov-Smirnov against the distribution functions (mu + 1)/2 and
+    # (mu^3 + 3 mu + 4)/8 of the densities 1/2 and (3/8)(1 + mu^2); the 1% critical
+    # value is 1.63 / n^(1/2)
+    crit = 1.63 / math.sqrt(iso.size)
+    assert _ks(iso, lambda m: (m + 1.0) / 2.0) < crit
+    assert _ks(dip, lambda m: (m ** 3 + 3.0 * m + 4.0) / 8.0) < crit
+    assert _ks(dip, lambda m: (m + 1.0) / 2.0) > 10 * crit
+    # moments: <mu^2> = 1/3 and 2/5, <mu^4> = 1/5 and 9/35, each within 4 sigma
+    n = iso.size
+    for m, m2, m4, m8 in ((iso, 1 / 3, 1 / 5, 1 / 9), (dip, 2 / 5, 9 / 35, 3 / 8 * (2 / 9 + 2 / 11))):
+        assert abs(np.mean(m ** 2) - m2) < 4 * math.sqrt((m4 - m2 * m2) / n)
+        assert abs(np.mean(m ** 4) - m4) < 4 * math.sqrt((m8 - m4 * m4) / n)
+        assert abs(np.mean(m)) < 4 * math.sqrt(m2 / n)
     with pytest.raises(ValueError):
-        rics.emission_cosine(U, "beamed")
+        rics.emission_cosine(w[1], w[2], w[3], "beamed")
 
 
 def _forced_case(pattern, n, sign):
@@ -192,10 +210,10 @@ def _forced_case(pattern, n, sign):
 
 @pytest.mark.parametrize("sign", [1.0, -1.0])
 @pytest.mark.parametrize("pattern", ["isotropic", "dipole"])
-def test_step_draws_the_emission_cosine_from_the_second_word(pattern, sign):
+def test_step_draws_the_emission_cosine_from_the_event_block(pattern, sign):
     # every positron scatters; the photons with eps >= 2 convert on the spot into a
     # pair moving along the photon, the others escape.  The recoils match the cosines
-    # drawn from the second word of each event's Philox block, energy is conserved
+    # drawn from the other words of each event's Philox block, energy is conserved
     # through recoil, pairs and escaped photons, and over the ensemble the mean photon
     # energy matches the pattern's average of eps(mu_r)
     n = 4000
@@ -205,7 +223,7 @@ def test_step_draws_the_emission_cosine_from_the_second_word(pattern, sign):
     k0, k1 = philox.seed_key(5)
     lo, hi = philox.split_id(ids)
     w = philox.philox4x32_10(0, lo, hi, philox.STREAM_RICS, k0, k1)
-    mu_r = rics.emission_cosine(philox.uniform24(w[1]), pattern)
+    mu_r = rics.emission_cosine(w[1], w[2], w[3], pattern)
     eps, un, dph = rics.emission(np.full(n, u0), b, mu_r)
     conv = eps >= 2.0
     c = st.counters[0]
