@@ -75,6 +75,19 @@ enum { PIC1D_CONV_IMMEDIATE = 0,   /* at the emission point (Sec. 3)            
        PIC1D_CONV_CURVATURE = 1 }; /* where its angle to the curved line reaches
                                       arcsin(2 m_e c^2 / E): s' = s +- R_curv asin */
 
+/* Direction of the de-excitation photon in the rest frame of the excited lepton
+ * (Appendix A.2-A.3).  The lab photon energy and the recoil follow from the
+ * rest-frame energy E_gamma(theta) of Appendix A.2, the lepton recoiling along B,
+ * boosted back with gamma_e = gamma (1+2b)^-1/2 (Eq. scatlim1; no boost where
+ * gamma_e < 1); the cosine from the lepton's motion is drawn from the second word of
+ * the event's Philox block.  The paper defers the pattern to an external reference:
+ * the non-perpendicular patterns are readings. */
+enum { PIC1D_EMIT_PERPENDICULAR = 0, /* cosine 0: eps = gamma (1 - (1+2b)^-1/2) (Eq.
+                                        perpemit), the lepton keeps gamma_e       */
+       PIC1D_EMIT_ISOTROPIC = 1,     /* cosine uniform on [-1, 1]                   */
+       PIC1D_EMIT_DIPOLE = 2 };      /* density 3/8 (1 + cosine^2), the classical
+                                        cyclotron pattern summed over polarisations */
+
 /* Initial pair plasma of a line (Sec. 3: homogeneous e-/e+ plasma). */
 enum { PIC1D_INIT_COLD = 0,    /* u = 0                                          */
        PIC1D_INIT_HOT = 1,     /* gamma log-uniform in [1, init_gamma_max], random sign */
@@ -121,7 +134,7 @@ typedef struct {
 
 typedef struct {
     int32_t n_lines;          /* >= 1 field lines, advanced together         */
-    int32_t pad0;
+    int32_t emission;         /* PIC1D_EMIT_*: rest-frame photon direction    */
     const pic1d_line* lines;  /* host, n_lines entries                       */
     double b_pole;            /* B_star / B_QED at the pole surface (10)     */
     double cfl;               /* c0/c (0.5), cells per step at c             */

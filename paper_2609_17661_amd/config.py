@@ -9,6 +9,7 @@ import copy
 RICS = {"off": 0, "exact": 1, "table": 2, "mlp": 3}
 CONVERSION = {"immediate": 0, "curvature": 1}
 PHOTON_FIELD = {"radial": 0, "disk": 1}
+EMISSION = {"perpendicular": 0, "isotropic": 1, "dipole": 2}
 INIT = {"cold": 0, "hot": 1, "stream": 2, "empty": 3}
 SPECIES = {"e_pair": 0, "p_pair": 1, "e_atm": 2, "ion": 3}
 
@@ -37,6 +38,8 @@ DEFAULTS = dict(
     frozen_field=False,
     annihilation=True,  # e-/e+ pairs annihilate in cells over n_max (Sec. 3)
     photon_field="radial",  # "radial": the radial beam (Sec. 2.2); "disk": the finite stellar disk (Sec. 5)
+    emission="perpendicular",   # rest-frame photon direction of an event (Appendix A.2-A.3):
+                                # "perpendicular" (Eq. perpemit), "isotropic", "dipole"
     seed=0,
     sort_interval=0,
     avg_start_step=-1,

@@ -282,7 +282,7 @@ PushArgs push_args(pic1d_state* st) {
     a.seg_base = st->seg_base; a.seg_cap = st->seg_cap; a.n_cur = st->n_cur; a.alloc = st->alloc;
     a.tile_prefix = st->tile_prefix; a.nseg = st->lay.nseg; a.tile = 64 * st->ppt;
     a.nlg = st->cfg.table_nlg; a.ns = st->cfg.table_ns;
-    a.pairs = st->cfg.pairs; a.conversion = st->cfg.conversion;
+    a.pairs = st->cfg.pairs; a.conversion = st->cfg.conversion; a.emission = st->cfg.emission;
     a.gravity = st->cfg.atmosphere && st->cfg.gravity;
     a.lines = st->dlines; a.E32 = st->E32; a.J = st->J; a.nodes = st->nodes; a.rc_nodes = st->rc_nodes;
     a.table = st->table; a.hist[0] = st->hist[0]; a.hist[1] = st->hist[1];

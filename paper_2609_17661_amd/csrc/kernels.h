@@ -29,7 +29,7 @@ struct PhotonRec {
     float off;
     float u_pre;      // lepton momentum before the recoil (sets gamma and eps)
     float b;          // B / B_QED at the emission point
-    float dir;        // direction of emission (+1 / -1 along s)
+    float mu;         // rest-frame emission cosine from the lepton's motion (0: perpendicular)
 };
 
 struct PushArgs {
@@ -46,6 +46,7 @@ struct PushArgs {
     int32_t tile;              // particles per tile (64 ppt)
     int32_t nlg, ns;
     int32_t pairs, conversion, gravity;
+    int32_t emission;          // PIC1D_EMIT_*
     const LineDev* lines;
     const float* E32;          // float32 copy of E (the gather needs no more)
     unsigned long long* J;

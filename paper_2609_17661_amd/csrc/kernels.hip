@@ -240,7 +240,9 @@ struct Counts {
 
 // Stochastic regime (b >= b_thr, Sec. 3): after the kick, a scattering event with
 // probability min(Ndot h, 1) from the Philox draw keyed by (step, id); the event
-// emits eps = gamma (1 - (1+2b)^-1/2) and leaves gamma / (1+2b)^1/2 (Appendix A).
+// emits eps = gamma (1 - (1+2b)^-1/2) and leaves gamma / (1+2b)^1/2 (Appendix A), or,
+// with an angular emission pattern, the photon leaves the excited lepton's rest frame
+// at the cosine drawn from the block's other words.
 __device__ __forceinline__ float stochastic_step(const PushArgs& a, const LineDev& L, const TileCtx& T, int line,
                                               int64_t k, int c0, float o0, float u, const Geo& g, float ndot,
                                               Counts& cnt) {
@@ -255,10 +257,16 @@ __device__ __forceinline__ float stochastic_step(const PushArgs& a, const LineDe
     ++cnt.events;
     const float gam = fsqrt(fmaf(u, u, 1.0f));
     const float dir = (u >= 0.0f) ? 1.0f : -1.0f;
-    const float eps = photon_energy(gam, g.b);
-    const float gnew = gam * frsq(fmaf(2.0f, g.b, 1.0f));
     const float u_pre = u;
-    u = dir * fsqrt(fmaxf((gnew - 1.0f) * (gnew + 1.0f), 0.0f));
+    float eps, mu_r = 0.0f;
+    if (a.emission == 0) {
+        eps = photon_energy(gam, g.b);
+        const float gnew = gam * frsq(fmaf(2.0f, g.b, 1.0f));
+        u = dir * fsqrt(fmaxf((gnew - 1.0f) * (gnew + 1.0f), 0.0f));
+    } else {
+        mu_r = emission_cosine(w, a.emission);
+        eps = angled_event(gam, g.b, mu_r, dir, u);
+    }
     if (a.pairs && eps >= 2.0f) {
         // record for the conversion kernel; lanes of a wavefront reserve their slots together
         const unsigned long long m = __ballot(1);
@@ -276,7 +284,7 @@ __device__ __forceinline__ float stochastic_step(const PushArgs& a, const LineDe
             p.off = o0;
             p.u_pre = u_pre;
             p.b = g.b;
-            p.dir = dir;
+            p.mu = mu_r;
         } else {
             set_error(&a.sc->err, -3);
         }
@@ -930,6 +938,21 @@ struct ConvRec {
     bool valid, convert;
 };
 
+// The lab photon energy of an angled event in float64 (the arithmetic of
+// angled_event); dir turns into the photon's direction along s, the lepton's sign
+// times that of c + beta_e.
+__device__ __forceinline__ double angled_photon(double gam, double q, double c, double& dir) {
+    const double ge = gam / q;
+    const double g2m1 = (ge - 1.0) * (ge + 1.0);
+    const bool boost = g2m1 > 0.0;
+    const double be = boost ? sqrt(g2m1) / ge : 0.0;
+    const double omb = boost ? 1.0 / (ge * ge * (1.0 + be)) : 1.0;
+    const double eg = (q - 1.0 / q) / (1.0 + sqrt(c * c + (1.0 - c) * (1.0 + c) / (q * q)));
+    const double dopp = c >= 0.0 ? fma(be, c, 1.0) : fma(be, 1.0 + c, omb);
+    if (c + be < 0.0) dir = -dir;
+    return ge * eg * dopp;
+}
+
 __device__ __forceinline__ ConvRec convert_record(const ConvertArgs& a, const int32_t* hist_in, const PhotonRec& p,
                                                   bool valid) {
     ConvRec c;
@@ -945,12 +968,14 @@ __device__ __forceinline__ ConvRec convert_record(const ConvertArgs& a, const in
     const int n = L.n_cells;
     const double ud = (double)p.u_pre;
     const double qd = sqrt(1.0 + 2.0 * (double)p.b);
-    const double eps = sqrt(1.0 + ud * ud) * (2.0 * (double)p.b) / (qd * (1.0 + qd));
+    double dir = ud >= 0.0 ? 1.0 : -1.0;
+    const double eps = p.mu == 0.0f ? sqrt(1.0 + ud * ud) * (2.0 * (double)p.b) / (qd * (1.0 + qd))
+                                    : angled_photon(sqrt(1.0 + ud * ud), qd, (double)p.mu, dir);
     bool ok = true;
     if (a.conversion != 0) {
         const double* rc = a.rc_nodes + L.node_base + p.cell;
         const double rcx = fma((double)p.off, rc[1] - rc[0], rc[0]);
-        const double sp = (double)p.cell + (double)p.off + (double)p.dir * rcx * L.inv_ds * asin(fmin(2.0 / eps, 1.0));
+        const double sp = (double)p.cell + (double)p.off + dir * rcx * L.inv_ds * asin(fmin(2.0 / eps, 1.0));
         ok = (sp >= 0.0) && (sp < (double)n);
         c.cell = ok ? (int)floor(sp) : 0;
         c.off = ok ? (float)(sp - (double)c.cell) : 0.0f;
@@ -960,7 +985,7 @@ __device__ __forceinline__ ConvRec convert_record(const ConvertArgs& a, const in
         const int* hc = hist_in + 4 * (size_t)(L.cell_base + c.cell);
         c.convert = (float)(hc[0] + hc[1] + hc[2] + hc[3]) < L.nmax;
         const double gp = 0.5 * eps;
-        c.up = p.dir * (float)sqrt(fmax((gp - 1.0) * (gp + 1.0), 0.0));
+        c.up = (float)(dir * sqrt(fmax((gp - 1.0) * (gp + 1.0), 0.0)));
     }
     return c;
 }

@@ -196,4 +196,46 @@ __device__ __forceinline__ float photon_energy(float gam, float b) {
     return gam * (2.0f * b) * frcp(q * (1.0f + q));
 }
 
+// Rest-frame emission cosine from words 2-4 of the event's Philox block (the first
+// decides the event).  Pattern 1: uniform on [-1, 1], 2 U1 - 1.  Pattern 2: density
+// 3/8 (1 + c^2), sampled as the mixture of the uniform (weight 3/4) and, when bits 0
+// and 1 of the second word are clear (weight 1/4), the density 3/2 c^2, whose |c| is
+// the largest of three uniforms and whose sign is bit 2.  Every draw is exact in
+// float32.
+__device__ __forceinline__ float emission_cosine(const uint4& w, int pattern) {
+    const float u1 = uniform24(w.y);
+    if (pattern == 1 || (w.y & 3u) != 0u) return fmaf(2.0f, u1, -1.0f);
+    const float top = fmaxf(u1, fmaxf(uniform24(w.z), uniform24(w.w)));
+    return (w.y & 4u) ? -top : top;
+}
+
+// One event whose photon leaves the excited lepton's rest frame at cosine c from its
+// motion (Appendix A.2-A.3).  Rest frame: E_gamma(theta) = (q - 1/q) / (1 + (c^2 +
+// (1 - c^2)/q^2)^1/2), the printed form without its 0/0 at c = +-1 (q = E_B/m_e c^2 =
+// (1+2b)^1/2); the lepton keeps E_e = q - E_gamma and momentum -E_gamma c along the
+// motion.  Both are boosted back with gamma_e = gamma / q (Eq. scatlim1; no boost where
+// gamma_e < 1).  1 - beta_e = 1/(gamma_e^2 (1 + beta_e)) keeps the Doppler factors
+// exact where they cancel: 1 + beta_e c for c < 0, and E_e - beta_e E_gamma c =
+// 1/(E_e + E_gamma c) + E_gamma c (1 - beta_e) for c >= 0 (rest-frame mass shell).
+// Returns the lab photon energy; u receives the lepton's momentum (dir = its sign
+// before the event).
+__device__ __forceinline__ float angled_event(float gam, float b, float c, float dir, float& u) {
+    const float q2 = fmaf(2.0f, b, 1.0f);
+    const float iq = frsq(q2), q = q2 * iq;
+    const float ge = gam * iq;
+    const float g2m1 = (ge - 1.0f) * (ge + 1.0f);
+    const bool boost = g2m1 > 0.0f;
+    const float be = boost ? fsqrt(g2m1) * frcp(ge) : 0.0f;
+    const float omb = boost ? frcp(ge * ge * (1.0f + be)) : 1.0f;
+    const float s2 = (1.0f - c) * (1.0f + c);
+    const float eg = (q - iq) * frcp(1.0f + fsqrt(fmaf(c, c, s2 * iq * iq)));
+    const float ee = q - eg, egc = eg * c;
+    const bool fwd = c >= 0.0f;
+    const float dopp = fwd ? fmaf(be, c, 1.0f) : fmaf(be, 1.0f + c, omb);
+    const float gn = ge * (fwd ? fmaf(egc, omb, frcp(ee + egc)) : fmaf(-be, egc, ee));
+    const float m = fsqrt(fmaxf((gn - 1.0f) * (gn + 1.0f), 0.0f));
+    u = (fmaf(be, ee, -egc) >= 0.0f) ? dir * m : -dir * m;
+    return ge * eg * dopp;
+}
+
 }  // namespace pic1d

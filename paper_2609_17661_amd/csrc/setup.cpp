@@ -96,6 +96,7 @@ const char* validate_config(const pic1d_config* c) {
         return "table_nlg * table_ns must not exceed 2^27";
     if (c->conversion != 0 && c->conversion != 1) return "unknown conversion mode";
     if (c->photon_field != 0 && c->photon_field != 1) return "unknown photon_field";
+    if (c->emission < 0 || c->emission > 2) return "unknown emission pattern";
     if (c->photon_field == 1 && c->rics_backend != 2 && c->rics_backend != 0)
         return "the finite-disk photon field needs the TABLE backend";
     if (c->sort_interval < 0) return "sort_interval must be >= 0";

@@ -10,7 +10,7 @@ import os
 
 import numpy as np
 
-from .config import CONVERSION, INIT, PHOTON_FIELD, RICS, SPECIES, complete_config
+from .config import CONVERSION, EMISSION, INIT, PHOTON_FIELD, RICS, SPECIES, complete_config
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpic1d.so")
 _lib = None
@@ -32,7 +32,7 @@ class CLine(ctypes.Structure):
 
 
 class CConfig(ctypes.Structure):
-    _fields_ = [("n_lines", ctypes.c_int32), ("pad0", ctypes.c_int32), ("lines", ctypes.POINTER(CLine)),
+    _fields_ = [("n_lines", ctypes.c_int32), ("emission", ctypes.c_int32), ("lines", ctypes.POINTER(CLine)),
                 ("b_pole", ctypes.c_double), ("cfl", ctypes.c_double), ("d0_cells", ctypes.c_double),
                 ("ppc0", ctypes.c_double), ("j_twist", ctypes.c_double), ("kT_keV", ctypes.c_double),
                 ("eta_min", ctypes.c_double), ("b_thr", ctypes.c_double), ("mass_ratio", ctypes.c_double),
@@ -195,6 +195,7 @@ def make_cconfig(cfg):
     c.frozen_field = int(bool(cfg["frozen_field"]))
     c.annihilation = int(bool(cfg["annihilation"]))
     c.photon_field = PHOTON_FIELD[cfg["photon_field"]]
+    c.emission = EMISSION[cfg["emission"]]
     c.seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
     c.sort_interval = int(cfg["sort_interval"])
     c.mlp_fallback_tol = float(cfg["mlp_fallback_tol"])

@@ -88,8 +88,19 @@ def _marginal_parents(ocfg, st_before, li):
         lo, hi = philox.split_id(P["id"])
         w = philox.philox4x32_10(st_before.step, lo, hi, philox.STREAM_RICS, k0, k1)
         U = philox.uniform24(w[0])
-        eps = rics.photon_energy(us, b)
+        if ocfg["emission"] == "perpendicular":
+            eps = rics.photon_energy(us, b)
+            dirn = np.where(us >= 0, 1.0, -1.0)
+            turn = np.zeros(us.shape, dtype=bool)
+        else:
+            mu_r = rics.emission_cosine(w[1], w[2], w[3], ocfg["emission"])
+            eps, _, dirn = rics.emission(us, b, mu_r)
+            # the photon's direction is the sign of mu_r + beta_e
+            ge = np.sqrt(1.0 + us * us) / np.sqrt(1.0 + 2.0 * b)
+            be = np.sqrt(np.maximum(1.0 - 1.0 / (ge * ge), 0.0))
+            turn = np.abs(mu_r + be) < 1e-5
         marg = near_b | (stoch & (np.abs(U - p) < PTOL + 1e-5 * p))
+        marg |= stoch & (U < p) & turn
         # drag limiter switch |F(p0)| tau_min = |p0| in either half step of the continuous regime
         cont = ~stoch
         if cont.any():
@@ -108,7 +119,6 @@ def _marginal_parents(ocfg, st_before, li):
         marg |= stoch & (U < p) & (np.abs(eps - 2.0) < PTOL * eps)
         if ocfg["pairs"]:
             ev = stoch & (U < p) & (eps >= 2.0)
-            dirn = np.where(us >= 0, 1.0, -1.0)
             if ocfg["conversion"] == "curvature":
                 sp = x0 + dirn * (rc / ln.ds) * np.arcsin(np.minimum(2.0 / np.maximum(eps, 2.0), 1.0))
                 tolx = 1e-5 * np.abs(sp - x0) + BAND

@@ -54,6 +54,17 @@ def test_invalid_configs_are_rejected(lib, bad):
     assert ei.value.code == -1
 
 
+def test_unknown_emission_pattern_is_rejected(lib):
+    c, keep = pic1d.make_cconfig(pic1d.complete_config(dict(workloads.CFG1, emission="dipole")))
+    n = ctypes.c_size_t(0)
+    assert lib.pic1d_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
+    c.emission = 3
+    assert lib.pic1d_workspace_size(ctypes.byref(c), ctypes.byref(n)) == -1
+    assert b"emission" in lib.pic1d_last_error(None)
+    with pytest.raises(KeyError):
+        pkg.workspace_size(dict(workloads.CFG1, emission="beamed"))
+
+
 def test_null_state_calls_fail_cleanly(lib):
     assert lib.pic1d_step(None, 1) == -1
     lib.pic1d_free(None)

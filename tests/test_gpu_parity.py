@@ -97,6 +97,12 @@ CASES = {
     "annihilation-table-atmosphere": workloads.small(n_cells=200, ppc=12, rics="table", table_nlg=64,
                                                      table_ns=96, pairs=True, conversion="curvature",
                                                      atmosphere=True, nmax_over_n0=1.5),
+    # angle-resolved de-excitation (Appendix A.2-A.3): the rest-frame cosine drawn per
+    # event, the photon's energy and direction and the recoil from the boost
+    "exact-curvature-isotropic": workloads.small(rics="exact", pairs=True, conversion="curvature",
+                                                 emission="isotropic", gamma_max=1e4),
+    "table-immediate-dipole": workloads.small(rics="table", table_nlg=64, table_ns=96, pairs=True,
+                                              emission="dipole", gamma_max=1e4),
 }
 
 
@@ -120,6 +126,10 @@ def test_step_parity(name):
         sim.step(1)   # let the state evolve between compared steps
     assert total["compared"] > 0
     assert total["excused"] <= max(3, 1e-3 * total["compared"])
+    if cfg.get("emission", "perpendicular") != "perpendicular":
+        c = sim.moments(0)["counters"]
+        _print("  events", c["events"], "pairs", c["pairs_created"], "escaped", c["photons_escaped"])
+        assert c["events"] > 100 and c["pairs_created"] > 20
     if name.endswith("newton"):
         n_newton = sim.moments(0)["counters"]["newton"]
         _print("  drag halves solved by Newton:", n_newton)
