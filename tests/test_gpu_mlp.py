@@ -200,7 +200,10 @@ def test_rics_eval_of_the_surrogate_matches_oracle():
                                 dict(init="cold", pairs=False, ppc=24),
                                 # tau_min = 68 steps: the implicit midpoint's fixed-point
                                 # refinement runs (Eq. implicit)
-                                dict(init="hot", gamma_max=1e4, pairs=True, eta_min=1.0, ppc=16)])
+                                dict(init="hot", gamma_max=1e4, pairs=True, eta_min=1.0, ppc=16),
+                                # angle-resolved events (dipole pattern) with the surrogate's Ndot
+                                dict(init="hot", gamma_max=1e4, pairs=True, conversion="curvature",
+                                     emission="dipole")])
 def test_step_parity_with_the_surrogate(kw):
     from paper_2609_17661_amd import Pic1D
 
