@@ -31,8 +31,9 @@ judged against the library's EXACT backend at the workload's particles.
 
 Cascade run (`cascade`; `--cascade` runs it alone): 64 lines of 32,768
 cells whose hot pair seed cascades up to n_max (about 4e8 particles), stepped
-from 100-step graphs in chunks; wall time, particle count and pair multiplicity
-per chunk, and k_push's HBM rate at the final count.  The RICS source is the
+from 100-step graphs in chunks; wall time, particle count and pairs created per
+chunk, the pair multiplicity M = n e c / j_psi at the end, and k_push's HBM rate
+at the final count.  The RICS source is the
 surrogate network (trained first on the GPU) with each line's table as its
 fallback where the network's error estimate on the line exceeds 1e-3; the
 line count on each source is reported.
@@ -409,7 +410,8 @@ def batched_path(steps, warmup):
 def cascade_run(chunks, chunk_steps, profile_steps, mlp_train_steps=0, fallback_tol=1e-3):
     """The combined cascade run (cfg5): 64 lines of 32,768 cells whose hot pair seed
     cascades up to n_max, stepped in chunks replayed from graphs; wall time, particle
-    count and pair multiplicity per chunk, then a profiled window for k_push's HBM
+    count and pairs created per chunk, the pair multiplicity M = n e c / j_psi at the
+    end, then a profiled window for k_push's HBM
     rate at the final particle count.  With mlp_train_steps > 0 the RICS source is
     the surrogate network, trained on the GPU first, with each line's table as its
     fallback where the network's error estimate on the line exceeds fallback_tol."""
@@ -456,7 +458,17 @@ def cascade_run(chunks, chunk_steps, profile_steps, mlp_train_steps=0, fallback_
         print(f"# cascade chunk {c}: {rows[-1]}", file=sys.stderr, flush=True)
     rp = timed_run(sim, profile_steps, 0, profile=True)
     bytes_per_launch = hbm_bytes_per_launch(rp)
-    gauss = max(sim.moments(li)["gauss_residual"] for li in range(sim.n_lines))
+    moms = [sim.moments(li) for li in range(sim.n_lines)]
+    gauss = max(m["gauss_residual"] for m in moms)
+    # the paper's pair multiplicity M = n e c / j_psi per cell (Sec. 4.3), n the e-/e+
+    # pair density in units of n0 and j_psi = j_twist n0 e c
+    M = [(m["n"][0] + m["n"][1]) / abs(cfg["j_twist"]) for m in moms]
+    Mall = np.concatenate(M)
+    multiplicity = {"definition": "M = n e c / j_psi per cell, n the e-/e+ pair density",
+                    "mean": float(Mall.mean()), "median": float(np.median(Mall)),
+                    "p99": float(np.quantile(Mall, 0.99)), "max": float(Mall.max()),
+                    "line_mean_min": float(min(x.mean() for x in M)),
+                    "line_mean_max": float(max(x.mean() for x in M))}
     src = ("surrogate network with per-line table fallback" if training else "TABLE") + " RICS"
     out = {"workload": f"cfg5: {sim.n_lines} lines, R_max log-uniform in [10, 100], 32768 cells each, hot pair "
                        f"seed {cfg['lines'][0]['ppc_init']} e-/e+ per cell (gamma to 1e4), "
@@ -464,7 +476,8 @@ def cascade_run(chunks, chunk_steps, profile_steps, mlp_train_steps=0, fallback_
                        f"m_i/m_e = 100, pairs (curvature), pair annihilation over n_max, {src}, 100-step graphs",
            "rics": rics_src, "init_seconds": t_init, "wall_seconds": wall, "steps": chunks * chunk_steps,
            "particles_start": n_start, "particles_end": rows[-1]["particles"],
-           "pair_multiplicity": pairs / seed_pairs, "pairs_annihilated": annihilated, "chunks": rows,
+           "pairs_created_per_seed_pair": pairs / seed_pairs, "multiplicity": multiplicity,
+           "pairs_annihilated": annihilated, "chunks": rows,
            "kernels_ms_at_end": rp["kernels_ms"],
            "k_push_ms_at_end": rp["push_avg_s"] * 1e3,
            "hbm_GBps_at_end": bytes_per_launch / rp["push_avg_s"] / 1e9,
