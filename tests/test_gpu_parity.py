@@ -243,6 +243,35 @@ def test_cfg4_full_size_density_limit_and_ledger(rics):
     assert m1["gauss_residual"] <= 1e-6
 
 
+def test_cfg4_full_size_angled_emission_sampled_parity():
+    """The hot R_max = 4 line at full size with angle-resolved events (isotropic
+    rest-frame pattern) and curvature conversion, in the autotuned launch shape,
+    after the tuner's trial steps, at the density limit: one step compared on a
+    sample (40,000 e- and 40,000 e+ and the pair members they make), with the
+    couplings through the line's cell counts (the pair gate at n_max, annihilation)
+    taken from the whole line; the count ledger and Gauss's law on the whole line."""
+    cfg = dict(workloads.CFG4, emission="isotropic", conversion="curvature")
+    ocfg = parity.oracle_config(cfg)
+    sim = _sim(cfg)
+    _print("cfg4 isotropic autotune", sim.autotune(trial_steps=3))
+    m0 = sim.moments(0)
+    before = parity.snapshot(sim)
+    sim.step(1)
+    m1 = sim.moments(0)
+    after = parity.snapshot(sim)
+    d = {k: m1["counters"][k] - m0["counters"][k] for k in m0["counters"]}
+    _print("cfg4 isotropic step", m1["step"], m1["count"], d, m1["gauss_residual"])
+    assert d["events"] > 20000 and d["pairs_created"] > 5000
+    grown = 2 * (d["pairs_created"] + d["atm_injected"] - d["annihilated"]) - d["absorbed"]
+    assert sum(m1["count"]) - sum(m0["count"]) == grown
+    assert m1["gauss_residual"] <= 1e-6
+    n_max = cfg["nmax_over_n0"] * cfg["ppc0"]
+    rep, _ = parity.sampled_compare(ocfg, before, after, 40000, np.random.default_rng(4), n_max=n_max)
+    _print("cfg4 isotropic sampled", rep)
+    assert rep["compared"] > 60000
+    assert rep["excused"] <= max(3, 1e-3 * rep["compared"])
+
+
 def test_cascade_gauss_and_counts_over_many_steps():
     cfg = workloads.small(n_cells=128, ppc=8, rics="exact", pairs=True, atmosphere=True,
                           conversion="curvature", sort_interval=3)
