@@ -707,14 +707,14 @@ int enqueue_step(pic1d_state* st) {
             const int pk = prof_begin(st, 5);
             hipLaunchKernelGGL(k_annih_plan, dim3(std::min(st->aux_blocks, (nt + 255) / 256)), dim3(256), 0,
                                st->stream, an);
-            hipLaunchKernelGGL(k_annih_gather, dim3(st->aux_blocks), dim3(256), 0, st->stream, an);
+            hipLaunchKernelGGL(k_annih_gather, dim3(GATHER_BLOCKS_PER_CU * st->n_cu), dim3(256), 0, st->stream, an);
             prof_end(st, pk);
         }
         // Ampere; its block 0 also plans the next push and advances the step counter
         const int pk = prof_begin(st, 2);
-        // 64 cells per wavefront, 16 with annihilation (k_field's cells per wavefront)
-        const int field_cells = f.annihilation ? 64 : 256;
-        hipLaunchKernelGGL(k_field, dim3(std::min(4 * st->aux_blocks, (nt + field_cells - 1) / field_cells)), dim3(256),
+        // 64 cells per wavefront, 4 with annihilation (k_field's cells per wavefront)
+        const int field_cells = f.annihilation ? 16 : 256;
+        hipLaunchKernelGGL(k_field, dim3(std::min(16 * st->aux_blocks, (nt + field_cells - 1) / field_cells)), dim3(256),
                            0, st->stream, f, book_args(st));
         prof_end(st, pk);
         st->host_step += 1;

@@ -1548,12 +1548,13 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
         f.an.ann_ctl[0] = 0;
         f.an.ann_ctl[1] = 0;
     }
-    // Each wavefront takes FIELD_CPW consecutive cells per iteration (all 64 lanes
-    // when annihilation is off; 16 when on, so that more wavefronts share the
-    // selections of the cells over the limit).
+    // Each wavefront takes cpw consecutive cells per iteration (all 64 lanes
+    // when annihilation is off; 4 when on, so that the selections of the cells over
+    // the limit, which a wavefront runs one after another, spread over many
+    // wavefronts).
     __shared__ int sHist[4][256];            // per wavefront: the radix histogram of the selection
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int cpw = f.annihilation ? 16 : 64;
+    const int cpw = f.annihilation ? 4 : 64;
     const int wpb = blockDim.x >> 6;
     for (int gw = (blockIdx.x * wpb + wid) * cpw; gw < n; gw += gridDim.x * wpb * cpw) {
         const int g = gw + lane;
@@ -1656,33 +1657,46 @@ __global__ __launch_bounds__(256) void k_annih_gather(AnnihArgs a) {
     const int32_t* hist_out = a.hist[(step & 1) ^ 1];
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const int stride = gridDim.x * 256;
+    // a thread takes GATHER_U particles per pass and issues their cell and per-cell
+    // loads together, so that several loads are in flight per lane
+    constexpr int U = GATHER_U;
+    const int stride = gridDim.x * 256 * U;
     for (int l = 0; l < a.n_lines; ++l) {
         const int cb = a.lines[l].cell_base;
         for (int s = 0; s < 2; ++s) {
             const int seg = 4 * l + s;
             const int n = min(a.alloc[seg], a.seg_cap[seg]);
             const int64_t base = a.seg_base[seg];
-            for (int i0 = blockIdx.x * 256; i0 < n; i0 += stride) {      // block-uniform trip count
-                const int i = i0 + (int)threadIdx.x;
-                const int c = i < n ? a.cell[base + i] : DEAD_CELL;
-                const int g = c != DEAD_CELL ? cb + c : 0;
-                const bool cand = c != DEAD_CELL && a.ann_k[g] != 0;
-                if (__ballot(cand) == 0ull) continue;                     // wave-uniform
-                int leader;
-                const unsigned long long mm = match_key(g, cand, leader);
-                int r0 = 0;
-                if (cand && lane == leader) r0 = atomicAdd(&a.ann_fill[2 * (size_t)g + s], __popcll(mm));
-                const int r = __shfl(r0, leader, 64) + __popcll(mm & below);
-                if (!cand) continue;
-                const int* h = hist_out + 4 * (size_t)g;
-                if (r >= h[s]) {              // counts and particles disagree: cannot happen
-                    set_error(&a.sc->err, -4);
-                    continue;
+            for (int i0 = blockIdx.x * 256 * U; i0 < n; i0 += stride) {      // block-uniform trip count
+                int cu[U], ku[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * 256 + (int)threadIdx.x;
+                    cu[u] = i < n ? a.cell[base + i] : DEAD_CELL;
                 }
-                const int64_t rec = (int64_t)a.ann_off[g] + (s ? h[0] : 0) + r;
-                a.cand_key[rec] = annih_key(step, a.id[base + i], a.key0, a.key1);
-                a.cand_slot[rec] = i;
+#pragma unroll
+                for (int u = 0; u < U; ++u) ku[u] = cu[u] != DEAD_CELL ? a.ann_k[cb + cu[u]] : 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * 256 + (int)threadIdx.x;
+                    const int g = cu[u] != DEAD_CELL ? cb + cu[u] : 0;
+                    const bool cand = cu[u] != DEAD_CELL && ku[u] != 0;
+                    if (__ballot(cand) == 0ull) continue;                     // wave-uniform
+                    int leader;
+                    const unsigned long long mm = match_key(g, cand, leader);
+                    int r0 = 0;
+                    if (cand && lane == leader) r0 = atomicAdd(&a.ann_fill[2 * (size_t)g + s], __popcll(mm));
+                    const int r = __shfl(r0, leader, 64) + __popcll(mm & below);
+                    if (!cand) continue;
+                    const int* h = hist_out + 4 * (size_t)g;
+                    if (r >= h[s]) {              // counts and particles disagree: cannot happen
+                        set_error(&a.sc->err, -4);
+                        continue;
+                    }
+                    const int64_t rec = (int64_t)a.ann_off[g] + (s ? h[0] : 0) + r;
+                    a.cand_key[rec] = annih_key(step, a.id[base + i], a.key0, a.key1);
+                    a.cand_slot[rec] = i;
+                }
             }
         }
     }
