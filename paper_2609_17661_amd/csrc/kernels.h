@@ -19,7 +19,7 @@ constexpr int SORT_SUB = 8;                     // sort key: cell and offset in 
 constexpr int SCAN_CELLS = 256;                 // cells per chunk of the sort's scan (one block)
 
 constexpr int GATHER_U = 4;                     // particles per thread and pass of the annihilation gather
-constexpr int GATHER_BLOCKS_PER_CU = 8;         // its blocks per CU
+constexpr int GATHER_BLOCKS_PER_CU = 16;        // its blocks per CU
 
 constexpr int PHOTON_REPL = 256;                // append regions of the photon buffer (one per wavefront
                                                 // slot of a block and block mod 64: spreads the reservations)
