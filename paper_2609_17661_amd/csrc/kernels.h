@@ -147,7 +147,8 @@ struct AnnihArgs {
     int32_t* ann_k;             // per global cell: pairs to annihilate this step, 0 if none
     int32_t* ann_off;           // per global cell: first candidate record (e- then e+)
     int32_t* ann_fill;          // per global cell and species 0/1: candidates recorded
-    int32_t* ann_ctl;           // [0] records allocated, [1] cells over the limit (this step)
+    int32_t* ann_ctl;           // [0] records allocated, [1] cells over the limit (this step),
+                                //   [2] its copy for the field kernel
     uint64_t* cand_key;         // candidate records: ranking key ...
     int32_t* cand_slot;         // ... and slot within its species segment
     int64_t cand_cap;           // records available

@@ -1548,13 +1548,13 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
         f.an.ann_ctl[0] = 0;
         f.an.ann_ctl[1] = 0;
     }
-    // Each wavefront takes cpw consecutive cells per iteration (all 64 lanes
-    // when annihilation is off; 4 when on, so that the selections of the cells over
-    // the limit, which a wavefront runs one after another, spread over many
-    // wavefronts).
+    // Each wavefront takes cpw consecutive cells per iteration: all 64 lanes, or 4
+    // in a step where some cell is over the limit, so that the selections, which a
+    // wavefront runs one after another, spread over many wavefronts (the grid is
+    // sized for 4; with 64 most of its blocks find no cells).
     __shared__ int sHist[4][256];            // per wavefront: the radix histogram of the selection
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int cpw = f.annihilation ? 4 : 64;
+    const int cpw = (f.annihilation && f.an.ann_ctl[2] != 0) ? 4 : 64;
     const int wpb = blockDim.x >> 6;
     for (int gw = (blockIdx.x * wpb + wid) * cpw; gw < n; gw += gridDim.x * wpb * cpw) {
         const int g = gw + lane;
@@ -1652,7 +1652,11 @@ __device__ __forceinline__ unsigned long long match_key(int key, bool active, in
 // limit records its key and slot.  Exits at once when no cell is over it.  Lanes
 // of a wavefront in the same cell reserve their records with one atomic.
 __global__ __launch_bounds__(256) void k_annih_gather(AnnihArgs a) {
-    if (a.sc->err != 0 || a.ann_ctl[1] == 0) return;
+    if (a.sc->err != 0) return;
+    // a copy of the over-limit flag for k_field, which clears [1] for the next step
+    // while its other blocks still need to know
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ann_ctl[2] = a.ann_ctl[1];
+    if (a.ann_ctl[1] == 0) return;
     const uint64_t step = a.sc->step;
     const int32_t* hist_out = a.hist[(step & 1) ^ 1];
     const int lane = threadIdx.x & 63;
