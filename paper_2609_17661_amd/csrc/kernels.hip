@@ -1664,25 +1664,25 @@ __global__ __launch_bounds__(256) void k_annih_gather(AnnihArgs a) {
     // a thread takes GATHER_U particles per pass and issues their cell and per-cell
     // loads together, so that several loads are in flight per lane
     constexpr int U = GATHER_U;
-    const int stride = gridDim.x * 256 * U;
+    const int64_t stride = (int64_t)gridDim.x * 256 * U;     // (a segment may hold nearly 2^31 slots)
     for (int l = 0; l < a.n_lines; ++l) {
         const int cb = a.lines[l].cell_base;
         for (int s = 0; s < 2; ++s) {
             const int seg = 4 * l + s;
             const int n = min(a.alloc[seg], a.seg_cap[seg]);
             const int64_t base = a.seg_base[seg];
-            for (int i0 = blockIdx.x * 256 * U; i0 < n; i0 += stride) {      // block-uniform trip count
+            for (int64_t i0 = (int64_t)blockIdx.x * 256 * U; i0 < n; i0 += stride) {   // block-uniform trip count
                 int cu[U], ku[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int i = i0 + u * 256 + (int)threadIdx.x;
+                    const int64_t i = i0 + u * 256 + (int)threadIdx.x;
                     cu[u] = i < n ? a.cell[base + i] : DEAD_CELL;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) ku[u] = cu[u] != DEAD_CELL ? a.ann_k[cb + cu[u]] : 0;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int i = i0 + u * 256 + (int)threadIdx.x;
+                    const int i = (int)(i0 + u * 256 + (int)threadIdx.x);    // < n where used
                     const int g = cu[u] != DEAD_CELL ? cb + cu[u] : 0;
                     const bool cand = cu[u] != DEAD_CELL && ku[u] != 0;
                     if (__ballot(cand) == 0ull) continue;                     // wave-uniform
