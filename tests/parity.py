@@ -195,6 +195,35 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
     rep = dict(compared=0, excused=0, max_dx=0.0, max_du_rel=0.0, max_dE=0.0, new=0)
     ambiguous = {}
 
+    def refill_ambiguous(li, excused_ids):
+        """Per cell, how many atmosphere (e-, ion) counts before the refill may differ
+        between the float32 and float64 paths: an atmosphere particle within BAND of a
+        face (its cell and the neighbour across that face), or at a wall (absorbed or
+        not), or an excused one.  A refill differs from the oracle's by at most that
+        many particles per species in a cell."""
+        pre = oracle_from_snapshot(dict(ocfg, atmosphere=False, annihilation=False), snap_before)
+        pic.step(pre)
+        amb = {}
+        for s in (2, 3):
+            x = pre.parts[li][s]["x"]
+            ids = pre.parts[li][s]["id"]
+            near = np.abs(x - np.round(x)) < BAND
+            for b in np.round(x[near]).astype(np.int64):
+                for c in (int(b) - 1, int(b)):
+                    amb[c] = amb.get(c, 0) + 1
+            for i, xx in zip(ids, x):
+                if int(i) in excused_ids:
+                    c = int(math.floor(xx))
+                    amb[c] = amb.get(c, 0) + 1
+            # absorbed on one side only: the particle kept by the other path lies
+            # within BAND of a wall
+            B = snap_before["lines"][li]["parts"][s]
+            xb = B["cell"].astype(np.float64) + B["off"].astype(np.float64)
+            walls = (xb < 1.0) | (xb > pre.lines[li].n - 1.0)
+            for c in np.floor(np.clip(xb[walls], 0, pre.lines[li].n - 1)).astype(np.int64):
+                amb[int(c)] = amb.get(int(c), 0) + 1
+        return amb
+
     def annihilation_ambiguous(li, excused_ids):
         """Cells whose end-of-step count (before annihilation) may differ between the
         float32 and float64 paths: a particle within BAND of one of their faces, or
@@ -219,7 +248,8 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
         n = ln.n
         marg, scattered = _marginal_parents(ocfg, before, li)
         excused_new = _child_ids(ocfg, before.step, marg)
-        atm_cells_excused = set()
+        atm_cells_excused = {}  # cell -> one-sided injected atmosphere particles excused
+        atm_amb = None
         ann_excused = {}        # cell -> one-sided e-/e+ excused by an ambiguous annihilation
         parent_x = None
         maxcount = 1
@@ -262,13 +292,18 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
             bad_cell = raw_cell & ~near_edge & ~exc
             tolx = np.where(is_new, xtol_new if xtol_new is not None else xtol, xtol)
             if ocfg["conversion"] == "curvature" and is_new.any():
-                # a pair member sits at the parent's position plus R_curv arcsin(2/eps),
-                # computed from the parent's float32 state: its error scales with that
-                # distance (and with the distance from the wall, for the rounding of x)
+                # a pair member sits at the parent's position plus the distance
+                # d = (R_curv / ds) arcsin(2/eps), computed from the parent's float32
+                # state: a relative error e of eps moves it by d e tan(t)/t, t = d ds / R_curv
+                # the angle (arcsin's slope), with e within the momentum tolerance
                 if parent_x is None:
                     parent_x = _child_parent_x(ocfg, snap_before["step"], snap_before["lines"][li]["parts"])
-                dist = np.array([abs(x - parent_x.get(int(i), x)) for i, x in zip(common, xo)])
-                tolx = np.where(is_new, np.maximum(tolx, 1e-5 * (np.abs(xo) + dist) + xtol), tolx)
+                xp = np.array([parent_x.get(int(i), x) for i, x in zip(common, xo)])
+                dist = np.abs(xo - xp)
+                _, _, _, rcur = ln.geometry_at(np.clip(xp, 0.0, n))
+                theta = np.minimum(dist * ln.ds / rcur, 0.5 * math.pi * (1.0 - 1e-9))
+                slope = np.where(theta > 1e-8, np.tan(theta) / np.maximum(theta, 1e-8), 1.0)
+                tolx = np.where(is_new, np.maximum(tolx, utol * dist * slope + xtol), tolx)
             dx = np.abs(xg - xo)
             raw_x = dx > tolx
             bad_x = raw_x & ~exc
@@ -338,7 +373,13 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
                         else:
                             k = int(np.nonzero(O["id"] == np.uint64(pid))[0][0])
                             cell = int(math.floor(O["x"][k]))
-                        atm_cells_excused.add(cell)
+                        if atm_amb is None:
+                            atm_amb = refill_ambiguous(li, marg | excused_new)
+                        key = (cell, s)
+                        atm_cells_excused[key] = atm_cells_excused.get(key, 0) + 1
+                        if atm_cells_excused[key] > atm_amb.get(cell, 0):
+                            raise AssertionError(f"line {li} species {s}: new atmosphere particle {pid} only on the "
+                                                 f"{side} in cell {cell}, beyond what ambiguous counts there allow")
                         rep["excused"] += 1
                         continue
                     raise AssertionError(f"line {li} species {s}: new particle {pid} only on the {side}")
@@ -346,8 +387,8 @@ def compare_step(ocfg, snap_before, snap_after, xtol=XTOL, utol=UTOL, xtol_new=N
             maxcount = max(maxcount, int(cnt.max()) if cnt.size else 1)
         # an atmosphere cell may differ by the refill of one excused particle only
         if atm_cells_excused:
-            rep["atm_cells_excused"] = sorted(atm_cells_excused)
-            for c in atm_cells_excused:
+            rep["atm_cells_excused"] = sorted(c for c, _ in atm_cells_excused)
+            for c, _ in atm_cells_excused:
                 assert min(c, n - 1 - c) < ln.atm_depth + 2, f"atmosphere mismatch outside the layer, cell {c}"
         if not check_field:
             continue
