@@ -53,11 +53,12 @@ def _assert_same(a, b):
                 assert np.array_equal(pa[k], pb[k]), k
 
 
-def test_ragged_lines_step_parity():
-    cfg = _ragged()
+@pytest.mark.parametrize("emission", ["perpendicular", "dipole"])
+def test_ragged_lines_step_parity(emission):
+    cfg = _ragged(emission=emission)
     ocfg = parity.oracle_config(cfg)
     sim = Pic1D(cfg)
-    _print("ragged lines", [(l["r_eq"], l["n_cells"], l["ppc_init"]) for l in cfg["lines"]])
+    _print("ragged lines", emission, [(l["r_eq"], l["n_cells"], l["ppc_init"]) for l in cfg["lines"]])
     for k in range(3):
         before = parity.snapshot(sim)
         sim.step(1)
