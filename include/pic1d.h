@@ -314,6 +314,7 @@ typedef struct {
     double ms_per_step_after;    /* with the chosen shape                          */
     int32_t push_ppt;            /* particles per lane of a particle-kernel tile   */
     int32_t deposit_window;      /* cells of a wavefront's LDS deposit window      */
+    int32_t sort_granularity;    /* sort bins per cell                             */
 } pic1d_tune_out;
 
 /* Autotuner of the launch shape: times trial_steps real steps (at least one
@@ -321,7 +322,8 @@ typedef struct {
  * 16 particles per lane; the deposit window, 128 or 64 cells for the TABLE
  * backend, 32 or 64 for OFF and EXACT, wherever that shape is built), push
  * blocks per CU in {1,2,3,4,6,8}, the XCD-aware tile walk on/off, sort_interval
- * in {1,2,5,10,25,50,100} -- one knob at a time, and keeps the fastest; a tile
+ * in {1,2,5,10,25,50,100}, then (when sorting) 8, 16 or 32 sort bins per cell
+ * -- one knob at a time, and keeps the fastest; a tile
  * shape or block count other than the starting one must beat it again when the
  * two are timed alternately twice.  The trial steps advance the simulation; the
  * physics does not depend on these choices (particle order and launch shape do
@@ -334,6 +336,14 @@ int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out);
  * results do not depend on it.  Errors: EINVAL (a shape that is not built),
  * ESTATE. */
 int pic1d_set_push_shape(pic1d_state* st, int32_t blocks_per_cu, int32_t ppt, int32_t window);
+
+/* Granularity of the cell sort: after a sort every species' particles are in
+ * nondecreasing order of cell * bins_per_cell + min(floor(offset *
+ * bins_per_cell), bins_per_cell - 1) (8 on a new state; a power of two, 1 to
+ * 32).  Finer bins group the particles that cross a cell face more tightly in
+ * memory at a higher counting cost.  The results do not depend on it.  Waits
+ * for the stream and drops captured graphs.  Errors: EINVAL, ESTATE. */
+int pic1d_set_sort_granularity(pic1d_state* st, int32_t bins_per_cell);
 
 /* The surrogate's error estimate on one line and whether the line uses its
  * table instead (MLP backend with mlp_fallback_tol > 0; otherwise *error = -1 and

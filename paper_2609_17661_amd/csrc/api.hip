@@ -106,6 +106,7 @@ struct pic1d_state {
     int push_bpc = 0;                              // push blocks per CU
     int ppt = PUSH_PPT_DEFAULT;                    // particles per lane per tile of the push
     int ww = 0;                                    // deposit window of the push (cells)
+    int sort_sub = SORT_SUB_DEFAULT;               // sort bins per cell
     int n_table_lines = 0;                         // MLP with table fallback: lines on their table
     int push_blocks_table = 0;                     // ... and the table kernel's blocks for them
     int graph_steps = 0;                           // requested steps per graph; 0 = eager
@@ -215,7 +216,7 @@ void carve(Carver& cv, const Layout& L, pic1d_state* st) {
     s->j_sum = cv.take<double>(L.n_cells);
     s->hist[0] = cv.take<int32_t>(4 * (size_t)L.n_cells);
     s->hist[1] = cv.take<int32_t>(4 * (size_t)L.n_cells);
-    s->bins = cv.take<int4>((size_t)SORT_SUB * L.n_cells);
+    s->bins = cv.take<int4>((size_t)SORT_SUB_MAX * L.n_cells);
     s->chunk_sum = cv.take<int4>(L.n_chunks);
     s->chunk_line = cv.take<int32_t>(L.n_chunks);
     s->line_chunk0 = cv.take<int32_t>(L.n_lines + 1);
@@ -389,7 +390,7 @@ int launch_sort(pic1d_state* st) {
     s.tile_prefix = st->tile_prefix;
     s.nseg = st->lay.nseg; s.tile = 64 * st->ppt; s.lines = st->dlines; s.hist[0] = st->hist[0]; s.hist[1] = st->hist[1];
     s.bins = st->bins; s.chunk_sum = st->chunk_sum; s.chunk_line = st->chunk_line; s.line_chunk0 = st->line_chunk0;
-    s.n_chunks = st->lay.n_chunks; s.n_bins = SORT_SUB * st->lay.n_cells;
+    s.n_chunks = st->lay.n_chunks; s.n_bins = st->sort_sub * st->lay.n_cells; s.sub = st->sort_sub;
     s.new_count = st->new_count; s.sc = st->sc;
     const int pk = prof_begin(st, 4);
     hipLaunchKernelGGL(k_sort_zero, dim3(st->aux_blocks), dim3(256), 0, st->stream, s);
@@ -835,6 +836,17 @@ int pic1d_set_push_shape(pic1d_state* st, int32_t blocks_per_cu, int32_t ppt, in
     return set_push_shape(st, blocks_per_cu, ppt, window);
 }
 
+int pic1d_set_sort_granularity(pic1d_state* st, int32_t bins_per_cell) {
+    if (!st || bins_per_cell < 1 || bins_per_cell > SORT_SUB_MAX || (bins_per_cell & (bins_per_cell - 1)) != 0)
+        return fail(st, PIC1D_EINVAL, "bad arguments");
+    if (st->frozen) return fail(st, PIC1D_ESTATE, "state frozen by an earlier error");
+    // captured graphs hold the old bin count in their sort launches
+    HIP_TRY(st, hipStreamSynchronize(st->stream));
+    st->drop_graphs();
+    st->sort_sub = bins_per_cell;
+    return PIC1D_OK;
+}
+
 int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out) {
     if (!st || trial_steps < 1 || !out) return fail(st, PIC1D_EINVAL, "bad arguments");
     if (st->frozen) return fail(st, PIC1D_ESTATE, "state frozen by an earlier error");
@@ -948,6 +960,21 @@ int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out) {
         }
         st->cfg.sort_interval = best_s;
     }
+    // 4. sort bins per cell (finer bins cost more counting but group the particles
+    //    that cross a face more tightly; pays where sorts are rare)
+    if (!rc && st->cfg.sort_interval > 0) {
+        const int g0 = st->sort_sub;
+        int best_g = g0;
+        const int cand_g[] = {8, 16, 32};
+        for (int c : cand_g) {
+            if (rc || c == g0) continue;
+            st->sort_sub = c;
+            double t = 0.0;
+            rc = measure(t);
+            if (!rc && t < best) { best = t; best_g = c; }
+        }
+        st->sort_sub = best_g;
+    }
     st->drop_graphs();
     st->graph_len = graph_length(st, st->graph_steps);
     st->prof_on = prof;
@@ -959,6 +986,7 @@ int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out) {
     out->deposit_window = st->ww;
     out->xcd_walk = st->xcd_walk;
     out->sort_interval = st->cfg.sort_interval;
+    out->sort_granularity = st->sort_sub;
     out->n_trials = trials;
     out->ms_per_step_before = base;
     out->ms_per_step_after = best;

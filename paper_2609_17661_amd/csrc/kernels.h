@@ -15,7 +15,8 @@ constexpr int PUSH_PPT_DEFAULT = 8;             // consecutive particles per thr
                                                 // (a tile, 64 ppt particles, is one wavefront's work item;
                                                 // the other particle kernels take a tile per block)
 constexpr int CNT_REPL = 64;                    // replicas of every counter (spreads same-address atomics)
-constexpr int SORT_SUB = 8;                     // sort key: cell and offset in eighths of a cell
+constexpr int SORT_SUB_DEFAULT = 8;             // sort key: cell and offset in eighths of a cell ...
+constexpr int SORT_SUB_MAX = 32;                // ... or in up to 32 parts (a power of two)
 constexpr int SCAN_CELLS = 256;                 // cells per chunk of the sort's scan (one block)
 
 constexpr int GATHER_U = 4;                     // particles per thread and pass of the annihilation gather
@@ -200,12 +201,13 @@ struct SortArgs {
     int32_t tile;              // particles per tile (64 ppt)
     const LineDev* lines;
     int32_t* hist[2];          // counts per cell and species; current = hist[step & 1]
-    int4* bins;                // [cells * SORT_SUB]: counts, then cursors, per species
+    int4* bins;                // [cells * sub]: counts, then cursors, per species
     int4* chunk_sum;           // [n_chunks]: counts per chunk, then its first slot per species
     const int32_t* chunk_line; // [n_chunks]: line of each chunk of SCAN_CELLS cells
     const int32_t* line_chunk0;// [n_lines + 1]: first chunk of each line
     int32_t n_chunks;
-    int32_t n_bins;            // cells * SORT_SUB
+    int32_t n_bins;            // cells * sub
+    int32_t sub;               // sort bins per cell: a power of two up to SORT_SUB_MAX
     int32_t* new_count;        // [nseg]
     DevScalars* sc;
 };

@@ -1609,12 +1609,13 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
 }
 
 // ---------------------------------------------------------------------------
-// Sort by position (counting sort per segment on the key cell * SORT_SUB +
-// floor(offset * SORT_SUB)), dropping absorbed particles.  Ordering by eighths
-// of a cell, not only by cell, keeps a lane's consecutive particles together in
+// Sort by position (counting sort per segment on the key cell * sub +
+// floor(offset * sub), sub bins per cell, eight unless the launch tuner picks
+// another power of two), dropping absorbed particles.  Ordering by parts of a
+// cell, not only by cell, keeps a lane's consecutive particles together in
 // space, so that after a step the ones that crossed a face are grouped instead
-// of spread through every lane's slots.  Counts live in bins[cell * SORT_SUB +
-// sub] as one int4 (the four species):
+// of spread through every lane's slots.  Counts live in bins[cell * sub + k] as
+// one int4 (the four species):
 //   k_sort_zero     clears the bins
 //   k_sort_count    counts the live particles per bin
 //   k_sort_chunks   per chunk of SCAN_CELLS cells: its counts
@@ -1622,8 +1623,8 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
 //   k_sort_cursors  per chunk: each bin's first slot
 //   k_sort_scatter  every particle takes the next slot of its bin
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int sort_bin(int cell_base, int c, float off) {
-    return (cell_base + c) * SORT_SUB + min((int)(off * (float)SORT_SUB), SORT_SUB - 1);
+__device__ __forceinline__ int sort_bin(int cell_base, int c, float off, int sub) {
+    return (cell_base + c) * sub + min((int)(off * (float)sub), sub - 1);    // off * sub is exact
 }
 
 __device__ __forceinline__ int& int4_at(int4& v, int k) {
@@ -1728,7 +1729,7 @@ __global__ __launch_bounds__(256) void k_sort_count(SortArgs s) {
             const int i = i0 + q * PUSH_TPB + threadIdx.x;
             const int c = (i < ncur) ? s.cell[base + i] : DEAD_CELL;
             const bool live = c != DEAD_CELL;
-            const int bin = live ? sort_bin(L.cell_base, c, s.off[base + i]) : 0;
+            const int bin = live ? sort_bin(L.cell_base, c, s.off[base + i], s.sub) : 0;
             int leader;
             const unsigned long long m = match_key(bin, live, leader);
             if (live && lane == leader) atomicAdd(&int4_at(s.bins[bin], sp), __popcll(m));
@@ -1764,9 +1765,10 @@ __device__ __forceinline__ int4 cell_counts(const SortArgs& s, int chunk, int& g
     gcell = L.cell_base + c;
     int4 n = make_int4(0, 0, 0, 0);
     if (in) {
-#pragma unroll
-        for (int k = 0; k < SORT_SUB; ++k) {
-            const int4 b = s.bins[gcell * SORT_SUB + k];
+        const int4* bc = s.bins + (size_t)gcell * s.sub;
+#pragma unroll 8
+        for (int k = 0; k < s.sub; ++k) {
+            const int4 b = bc[k];
             n.x += b.x; n.y += b.y; n.z += b.z; n.w += b.w;
         }
     }
@@ -1811,10 +1813,11 @@ __global__ __launch_bounds__(256) void k_sort_cursors(SortArgs s) {
     if (!in) return;
     const int4 c0 = s.chunk_sum[blockIdx.x];
     int4 run = make_int4(c0.x + ex.x, c0.y + ex.y, c0.z + ex.z, c0.w + ex.w);
-#pragma unroll
-    for (int k = 0; k < SORT_SUB; ++k) {
-        const int4 b = s.bins[gcell * SORT_SUB + k];
-        s.bins[gcell * SORT_SUB + k] = run;
+    int4* bc = s.bins + (size_t)gcell * s.sub;
+#pragma unroll 8
+    for (int k = 0; k < s.sub; ++k) {
+        const int4 b = bc[k];
+        bc[k] = run;
         run = make_int4(run.x + b.x, run.y + b.y, run.z + b.z, run.w + b.w);
     }
 }
@@ -1845,7 +1848,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs s) {
                 puv = s.u[base + i];
                 pid = s.id[base + i];
             }
-            const int bin = live ? sort_bin(L.cell_base, c, pof) : 0;
+            const int bin = live ? sort_bin(L.cell_base, c, pof, s.sub) : 0;
             int leader;
             const unsigned long long m = match_key(bin, live, leader);
             int first = 0;

@@ -73,7 +73,7 @@ class CTuneOut(ctypes.Structure):
     _fields_ = [("push_blocks_per_cu", ctypes.c_int32), ("xcd_walk", ctypes.c_int32), ("sort_interval", ctypes.c_int32),
                 ("n_trials", ctypes.c_int32), ("ms_per_step_before", ctypes.c_double),
                 ("ms_per_step_after", ctypes.c_double), ("push_ppt", ctypes.c_int32),
-                ("deposit_window", ctypes.c_int32)]
+                ("deposit_window", ctypes.c_int32), ("sort_granularity", ctypes.c_int32)]
 
 
 class CMlpTrainConfig(ctypes.Structure):
@@ -123,6 +123,7 @@ _SIGS = {
     "pic1d_set_graph": (ctypes.c_int, [P, ctypes.c_int32]),
     "pic1d_autotune": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(CTuneOut)]),
     "pic1d_set_push_shape": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "pic1d_set_sort_granularity": (ctypes.c_int, [P, ctypes.c_int32]),
     "pic1d_testparticle_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "pic1d_testparticle_sweep": (ctypes.c_int, [ctypes.POINTER(CTpConfig), ctypes.c_int32, P, P, P, ctypes.c_size_t,
                                                 P]),
@@ -344,6 +345,10 @@ class Pic1D:
     def set_push_shape(self, blocks_per_cu, ppt, window):
         """Launch shape of the particle kernel: blocks per CU, particles per lane, deposit window (cells)."""
         self._check(self.lib.pic1d_set_push_shape(self.h, int(blocks_per_cu), int(ppt), int(window)))
+
+    def set_sort_granularity(self, bins_per_cell):
+        """Sort bins per cell (a power of two, 1 to 32); the results do not depend on it."""
+        self._check(self.lib.pic1d_set_sort_granularity(self.h, int(bins_per_cell)))
 
     def rics_line_info(self, line=0):
         """(surrogate error estimate on the line, whether the line uses its table)."""

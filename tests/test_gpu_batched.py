@@ -107,6 +107,7 @@ def test_autotune_changes_speed_not_results():
     assert out["n_trials"] >= 3
     assert out["push_blocks_per_cu"] in (1, 2, 3, 4, 6, 8)
     assert out["push_ppt"] in (4, 8, 16) and out["deposit_window"] in (32, 64)
+    assert out["sort_granularity"] in (8, 16, 32)
     assert out["ms_per_step_after"] <= out["ms_per_step_before"]
     steps = tuned.moments(0)["step"]
     ref.step(steps)

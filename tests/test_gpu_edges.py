@@ -136,3 +136,15 @@ def test_capacity_overflow_freezes_the_state():
         assert 0 < P["id"].size <= m["count"][s] <= 256
         assert np.unique(P["id"]).size == P["id"].size
         assert np.all((P["cell"] >= 0) & (P["cell"] < 64))
+
+
+@pytest.mark.parametrize("bad", [0, 3, 64, -8])
+def test_sort_granularity_outside_the_built_range_is_rejected(bad):
+    from paper_2609_17661_amd import Pic1dError
+    from paper_2609_17661_amd.pic1d import STATUS
+    sim = Pic1D(workloads.small(n_cells=64, ppc=4))
+    with pytest.raises(Pic1dError) as err:
+        sim.set_sort_granularity(bad)
+    assert STATUS[err.value.code] == "EINVAL"
+    sim.step(2)                       # the state is untouched
+    assert sim.moments(0)["step"] == 2

@@ -289,8 +289,10 @@ def test_cascade_gauss_and_counts_over_many_steps():
 # ---------------------------------------------------------------------------
 # determinism, sort invariance, errors
 # ---------------------------------------------------------------------------
-def _final(cfg, steps):
+def _final(cfg, steps, granularity=None):
     sim = _sim(cfg)
+    if granularity is not None:
+        sim.set_sort_granularity(granularity)
     sim.step(steps)
     out = {}
     for s in range(4):
@@ -305,12 +307,14 @@ def test_result_independent_of_sorting_and_bitwise_reproducible():
     a, Ea = _final(dict(base, sort_interval=0), 25)
     b, Eb = _final(dict(base, sort_interval=1), 25)
     c, Ec = _final(dict(base, sort_interval=7), 25)
+    d, Ed = _final(dict(base, sort_interval=1), 25, granularity=32)
+    e, Ee = _final(dict(base, sort_interval=2), 25, granularity=1)
     for s in range(4):
         for k in ("id", "cell", "off", "u"):
-            np.testing.assert_array_equal(a[s][k], b[s][k])
-            np.testing.assert_array_equal(a[s][k], c[s][k])
-    np.testing.assert_array_equal(Ea, Eb)
-    np.testing.assert_array_equal(Ea, Ec)
+            for other in (b, c, d, e):
+                np.testing.assert_array_equal(a[s][k], other[s][k])
+    for other in (Eb, Ec, Ed, Ee):
+        np.testing.assert_array_equal(Ea, other)
 
 
 def test_annihilation_holds_cells_at_the_limit_independently_of_sorting():
@@ -349,29 +353,35 @@ def test_annihilation_holds_cells_at_the_limit_independently_of_sorting():
         np.testing.assert_array_equal(E, finals[0][1])
 
 
-def test_sort_orders_particles_by_position():
-    """After a sort every species array is in position order by eighths of a cell
-    (cell * 8 + floor(8 * offset) nondecreasing), absorbed particles are gone, and
-    the set of particles is unchanged."""
+def _sort_key(P, g):
+    return P["cell"].astype(np.int64) * g + np.minimum((P["off"].astype(np.float64) * g).astype(np.int64), g - 1)
+
+
+@pytest.mark.parametrize("granularity", [None, 1, 16, 32])
+def test_sort_orders_particles_by_position(granularity):
+    """After a sort every species array is in position order by parts of a cell
+    (cell * g + floor(g * offset) nondecreasing, g = 8 bins per cell unless set
+    otherwise), absorbed particles are gone, and the set of particles is unchanged."""
     cfg = workloads.small(n_cells=300, ppc=20, rics="exact", init="hot", gamma_max=1e3, pairs=True,
                           atmosphere=True, sort_interval=5)
     sim = _sim(cfg)
     first = [sim.get_particles(0, s) for s in range(4)]
     for P in first:                    # the initial plasma is sorted once after init
-        key = P["cell"].astype(np.int64) * 8 + np.minimum((P["off"] * 8).astype(np.int64), 7)
-        assert np.all(np.diff(key) >= 0)
+        assert np.all(np.diff(_sort_key(P, 8)) >= 0)
+    g = 8
+    if granularity is not None:
+        sim.set_sort_granularity(granularity)
+        g = granularity
     sim.step(4)
     before = [sim.get_particles(0, s) for s in range(4)]
     sim.step(1)                        # step 5: push, appends, then the sort
     after = [sim.get_particles(0, s) for s in range(4)]
     unsorted = 0
     for P in before:
-        key = P["cell"].astype(np.int64) * 8 + np.minimum((P["off"] * 8).astype(np.int64), 7)
-        unsorted += int(np.sum(np.diff(key) < 0))
+        unsorted += int(np.sum(np.diff(_sort_key(P, g)) < 0))
     assert unsorted > 0                # four pushes of a hot plasma do disorder it
     for P in after:
-        key = P["cell"].astype(np.int64) * 8 + np.minimum((P["off"] * 8).astype(np.int64), 7)
-        assert np.all(np.diff(key) >= 0)
+        assert np.all(np.diff(_sort_key(P, g)) >= 0)
         assert len(np.unique(P["id"])) == len(P["id"])
     m = sim.moments(0)
     assert [len(P["id"]) for P in after] == list(m["count"])
