@@ -662,7 +662,10 @@ int enqueue_step(pic1d_state* st) {
             ca.photons = st->photons; ca.n_photons = st->n_photons; ca.photon_region = st->lay.photon_region;
             ca.conversion = st->cfg.conversion;
             ca.key0 = (uint32_t)(st->cfg.seed & 0xFFFFFFFFu); ca.key1 = (uint32_t)(st->cfg.seed >> 32);
-            conv_blocks = st->aux_blocks;
+            // one block per CU: every block first scans the record regions' fills, which
+            // is most of the launch where few photons were recorded (four per CU cost
+            // 1 us more a step on a quiet line and bought nothing with 2.5e5 pairs a step)
+            conv_blocks = st->n_cu;
         }
         ca.sc = st->sc;
         if (st->cfg.atmosphere && st->lay.n_layer > 0) {
