@@ -714,12 +714,13 @@ int enqueue_step(pic1d_state* st) {
             hipLaunchKernelGGL(k_annih_gather, dim3(GATHER_BLOCKS_PER_CU * st->n_cu), dim3(256), 0, st->stream, an);
             prof_end(st, pk);
         }
-        // Ampere; its block 0 also plans the next push and advances the step counter
+        // Ampere; its last block plans the next push and advances the step counter
         const int pk = prof_begin(st, 2);
         // 64 cells per wavefront, 4 with annihilation (k_field's cells per wavefront)
         const int field_cells = f.annihilation ? 16 : 256;
-        hipLaunchKernelGGL(k_field, dim3(std::min(16 * st->aux_blocks, (nt + field_cells - 1) / field_cells)), dim3(256),
-                           0, st->stream, f, book_args(st));
+        // (and one more block for the bookkeeping)
+        hipLaunchKernelGGL(k_field, dim3(std::min(16 * st->aux_blocks, (nt + field_cells - 1) / field_cells) + 1),
+                           dim3(256), 0, st->stream, f, book_args(st));
         prof_end(st, pk);
         st->host_step += 1;
         if (st->cfg.sort_interval > 0 && st->host_step % st->cfg.sort_interval == 0) {

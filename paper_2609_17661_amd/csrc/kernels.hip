@@ -1197,6 +1197,30 @@ __global__ __launch_bounds__(256) void k_append(ConvertArgs ca, AtmArgs aa, int 
     else refill_atmosphere(aa, blockIdx.x - conv_blocks, gridDim.x - conv_blocks);
 }
 
+// Block-wide (256 threads) exclusive scan of one int; writes the block total.
+__device__ __forceinline__ int block_excl_scan(int v, int& total) {
+    __shared__ int sWave[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) sWave[w] = inc;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = sWave[i];
+        before += i < w ? t : 0;
+        total += t;
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
 // ---------------------------------------------------------------------------
 // Per-step bookkeeping shared by k_field and k_plan: live counts <- allocation
 // counters (clamped to capacity), tile plan of the next push.
@@ -1204,31 +1228,25 @@ __global__ __launch_bounds__(256) void k_append(ConvertArgs ca, AtmArgs aa, int 
 __device__ void bookkeeping(const BookArgs& b) {
     if (b.sc->err != 0) return;
     if (b.n_photons && threadIdx.x < PHOTON_REPL) b.n_photons[threadIdx.x] = 0;
-    __shared__ int sPart[256];
     const int nseg = b.nseg;
     const int per = (nseg + 255) / 256;
-    const int s0 = threadIdx.x * per;
-    int sum = 0;
-    for (int s = s0; s < min(s0 + per, nseg); ++s) {
+    const int s0 = threadIdx.x * per, s1 = min(s0 + per, nseg);
+    int sum = 0, n_last = 0;
+    for (int s = s0; s < s1; ++s) {
         const int n = min(b.alloc[s], b.seg_cap[s]);
         b.n_cur[s] = n;
         b.alloc[s] = n;
+        n_last = n;
         sum += (n + b.tile - 1) / b.tile;
     }
-    sPart[threadIdx.x] = sum;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const int v = (threadIdx.x >= o) ? sPart[threadIdx.x - o] : 0;
-        __syncthreads();
-        sPart[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int run = sPart[threadIdx.x] - sum;     // exclusive prefix
-    for (int s = s0; s < min(s0 + per, nseg); ++s) {
+    int total;
+    int run = block_excl_scan(sum, total);
+    for (int s = s0; s < s1; ++s) {
         b.tile_prefix[s] = run;
-        run += (b.n_cur[s] + b.tile - 1) / b.tile;
+        // (one segment per thread up to 256 segments: its count is still in a register)
+        run += ((per == 1 ? n_last : b.n_cur[s]) + b.tile - 1) / b.tile;
     }
-    if (threadIdx.x == 255) b.tile_prefix[nseg] = sPart[255];
+    if (threadIdx.x == 255) b.tile_prefix[nseg] = total;
 }
 
 // Bookkeeping kernel of every step (and after init, sort, set_particles): one block.
@@ -1255,29 +1273,6 @@ __device__ __forceinline__ uint64_t annih_key(uint64_t step, uint64_t id, uint32
     return ((uint64_t)w.y << 32) | (uint64_t)w.x;
 }
 
-// Block-wide (256 threads) exclusive scan of one int; writes the block total.
-__device__ __forceinline__ int block_excl_scan(int v, int& total) {
-    __shared__ int sWave[4];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += t;
-    }
-    if (lane == 63) sWave[w] = inc;
-    __syncthreads();
-    int before = 0;
-    total = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int t = sWave[i];
-        before += i < w ? t : 0;
-        total += t;
-    }
-    __syncthreads();
-    return before + inc - v;
-}
 
 // Every cell's k from its end-of-step counts, and for the cells over the limit a
 // run of candidate records (their e- then their e+), one allocation per block.
@@ -1533,20 +1528,27 @@ __device__ long long annihilate_cell(const AnnihArgs& a, const int32_t* hist_out
 // step counter; the cells read the running step from the copy the push left.
 __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
     if (f.sc->err != 0) return;
-    if (blockIdx.x == 0) {
-        bookkeeping(b);
-        if (threadIdx.x == 0 && b.sc->err == 0) b.sc->step += 1;
-    }
     const uint64_t step = f.sc->step_field;
     const int n = f.n_total;
     const int hin = (int)(step & 1);
     int* hist_in = f.hist[hin];
     int* hist_out = f.hist[hin ^ 1];
     const bool averaging = f.avg_start >= 0 && step >= (uint64_t)f.avg_start;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && f.annihilation) {
-        // the plan of the next step allocates from zero (no other block reads these)
-        f.an.ann_ctl[0] = 0;
-        f.an.ann_ctl[1] = 0;
+    // the last block plans the next push and advances the step counter, beside the
+    // cells' blocks rather than before one of them (none of them reads what it writes)
+    const int nb = gridDim.x - 1;
+    if ((int)blockIdx.x == nb) {
+        bookkeeping(b);
+        if (threadIdx.x == 0) {
+            if (b.sc->err == 0) b.sc->step += 1;
+            if (f.annihilation) {
+                // the plan of the next step allocates from zero (no other block reads these)
+                f.an.ann_ctl[0] = 0;
+                f.an.ann_ctl[1] = 0;
+            }
+            if (averaging) f.avg_count[0] += 1;
+        }
+        return;
     }
     // Each wavefront takes cpw consecutive cells per iteration: all 64 lanes, or 4
     // in a step where some cell is over the limit, so that the selections, which a
@@ -1556,7 +1558,7 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int cpw = (f.annihilation && f.an.ann_ctl[2] != 0) ? 4 : 64;
     const int wpb = blockDim.x >> 6;
-    for (int gw = (blockIdx.x * wpb + wid) * cpw; gw < n; gw += gridDim.x * wpb * cpw) {
+    for (int gw = (blockIdx.x * wpb + wid) * cpw; gw < n; gw += nb * wpb * cpw) {
         const int g = gw + lane;
         const bool own = lane < cpw && g < n;
         long long dJ = 0;        // this lane's cell: annihilation current and pairs removed
@@ -1605,7 +1607,6 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs f, BookArgs b) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) hist_in[4 * (size_t)g + s] = 0;
     }
-    if (averaging && blockIdx.x == 0 && threadIdx.x == 0) f.avg_count[0] += 1;
 }
 
 // ---------------------------------------------------------------------------
