@@ -12,7 +12,10 @@ Plain path (the headline `value`): the R_max = 30 line with 65,536 cells, 200
 e-/e+ per cell each (2.6e7 particles), surface atmosphere with ions at
 m_i/m_e = 100, pairs on with curvature conversion, capacity for 1e8 particles,
 TABLE RICS backend.  Launch shape and sort interval from the library's
-autotuner; the timed steps are launched eagerly or replayed from 100-step HIP
+autotuner; the timed region is the workload's whole run of 20,000 steps (after
+the tuner's trial steps and the warm-up), whose step time rises about threefold
+after the first two thousand steps as the line heats (`along_the_run`, per 2000
+steps); the timed steps are launched eagerly or replayed from 100-step HIP
 graphs, whichever a 200-step trial of each finds faster (`launch`).  The
 per-kernel breakdown and the push kernel's roofline come from HIP events around
 every launch in a profiled window of eagerly launched steps that follows the
@@ -201,10 +204,12 @@ def _counters(sim):
     return tot
 
 
-def timed_run(sim, steps, warmup, profile=True):
+def timed_run(sim, steps, warmup, profile=True, chunk=None):
     """Warm up, then time `steps` steps with HIP events on the library's stream;
     with profile, per-kernel event timing (pic1d_profile) is on during the timed
-    steps (profiled steps are launched eagerly, never from a captured graph)."""
+    steps (profiled steps are launched eagerly, never from a captured graph).
+    With `chunk`, an event every `chunk` steps also gives the step time along the
+    run (no host synchronisation inside the timed region)."""
     import torch
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -216,10 +221,26 @@ def timed_run(sim, steps, warmup, profile=True):
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
-    sim.step(steps)
+    marks = []
+    if chunk:
+        done = 0
+        while done < steps:
+            n = min(chunk, steps - done)
+            sim.step(n)
+            done += n
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            marks.append((done, e))
+    else:
+        sim.step(steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
+    along = []
+    prev_e, prev_n = ev0, 0
+    for n, e in marks:
+        along.append({"steps": [m0["step"] + prev_n, m0["step"] + n], "ms_per_step": prev_e.elapsed_time(e) / (n - prev_n)})
+        prev_e, prev_n = e, n
     prof = sim.profile_read()
     sim.profile(False)
     m1 = sim.moments(0)
@@ -227,7 +248,7 @@ def timed_run(sim, steps, warmup, profile=True):
     cnt = {k: c1[k] - c0[k] for k in c1}
     push = prof["push"]
     push_avg_s = push["ms"] / max(push["launches"], 1) * 1e-3
-    return dict(ms=ms, value=cnt["pushed"] / (ms * 1e-3), ms_per_step=ms / steps, counters=cnt,
+    return dict(ms=ms, value=cnt["pushed"] / (ms * 1e-3), ms_per_step=ms / steps, counters=cnt, along=along,
                 push_avg_s=push_avg_s, launches=push["launches"],
                 kernels_ms={k: v["ms"] / max(v["launches"], 1) for k, v in prof.items() if v["launches"]},
                 m0=m0, m1=m1)
@@ -489,18 +510,24 @@ def cascade_run(chunks, chunk_steps, profile_steps, mlp_train_steps=0, fallback_
     return out
 
 
-def plain_path(cfg, steps, warmup, profile_steps):
+def plain_path(cfg, steps, warmup, profile_steps, chunk=None, push_shape=None):
     """Autotune, pick eager or graph launches, time `steps` steps after `warmup`,
-    then a profiled window of eager launches for the kernel breakdown."""
+    then a profiled window of eager launches for the kernel breakdown.  With
+    push_shape (blocks per CU, particles per lane, window), that tile shape replaces
+    the tuner's (so that separate counter runs all profile the same kernel)."""
     from paper_2609_17661_amd import Pic1D
 
     sim = Pic1D(cfg, device="cuda:0")
     print(f"# init done: {cfg['lines'][0]}", file=sys.stderr, flush=True)
     tune = sim.autotune(trial_steps=10)        # launch shape and sort interval (results do not depend on them)
+    if push_shape:
+        sim.set_push_shape(*push_shape)
+        tune = dict(tune, push_blocks_per_cu=push_shape[0], push_ppt=push_shape[1], deposit_window=push_shape[2],
+                    shape_set_by_flag=True)
     print(f"# autotuned: {tune}", file=sys.stderr, flush=True)
     launch = pick_launch(sim)
     print(f"# launch: {launch}", file=sys.stderr, flush=True)
-    r = timed_run(sim, steps, warmup, profile=False)
+    r = timed_run(sim, steps, warmup, profile=False, chunk=chunk)
     # kernel breakdown and roofline: events around every launch, eager launches
     rp = timed_run(sim, profile_steps, 0, profile=True)
     sim.close()
@@ -514,6 +541,9 @@ def whole_step(r, steps):
     b = window_bytes(r) / steps
     t = r["ms_per_step"] * 1e-3
     return {"bytes_per_step": b, "achieved": b / t / 1e9, "unit": "GB/s", "frac": b / t / HBM_PEAK}
+
+
+ACTIVE_STEPS = 300     # timed steps of the hot-start leg
 
 
 def active_phase(cfg, steps, warmup, profile_steps):
@@ -539,7 +569,8 @@ def active_phase(cfg, steps, warmup, profile_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: cfg2's whole run of 20,000 steps; 300 for the other workloads)")
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--profile-steps", type=int, default=100,
                     help="eager steps with per-kernel events after the timed region")
@@ -552,6 +583,8 @@ def main():
                     help="drag-time variant: eta_min instead of the workload's 1e3 (App. C uses 1e2)")
     ap.add_argument("--mass-ratio", type=float, default=None,
                     help="mass-ratio variant: m_i/m_e instead of the workload's 100")
+    ap.add_argument("--push-shape", default=None,
+                    help="BPC,PPT,WINDOW: the particle kernel's tile shape instead of the tuner's (for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -587,6 +620,7 @@ def main():
         print(json.dumps({"surrogate_vs_table": surrogate_comparison(args.surrogate_steps, 30, args.mlp_train_steps)}),
               flush=True)
         return
+    steps = args.steps if args.steps is not None else (workloads.CFG2_STEPS if args.workload == "cfg2" else 300)
     cfg = dict({"cfg2": workloads.CFG2, "cfg1": workloads.CFG1, "cfg4": workloads.CFG4}[args.workload])
     cfg["rics"] = args.backend
     variant = ""
@@ -599,7 +633,11 @@ def main():
     if args.init is not None:
         cfg["lines"] = [dict(cfg["lines"][0], init=args.init, init_gamma_max=1.0e4)]
         variant += f", {args.init} start" + (" (gamma log-uniform to 1e4)" if args.init == "hot" else "")
-    r, rp, tune, launch = plain_path(cfg, args.steps, args.warmup, args.profile_steps)
+    # the step time changes along the run (the line heats after a couple of thousand
+    # steps): long runs also report it per 2000 steps
+    shape = tuple(int(x) for x in args.push_shape.split(",")) if args.push_shape else None
+    r, rp, tune, launch = plain_path(cfg, steps, args.warmup, args.profile_steps,
+                                     chunk=2000 if steps >= 4000 else None, push_shape=shape)
     roof = push_roofline(rp)
     # HBM bytes per k_push launch (rocprofv3), measured on the unmodified workload only
     traffic = measured_traffic(args.backend, args.workload) if not variant else None
@@ -617,7 +655,7 @@ def main():
         "value": r["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
@@ -629,7 +667,8 @@ def main():
                    "particles_start": sum(m0["count"]), "particles_end": sum(m1["count"]),
                    "step_window": [m0["step"], m1["step"]], "parallelism": "single GPU"},
         "roofline": roof,
-        "whole_step": whole_step(r, args.steps),
+        "whole_step": whole_step(r, steps),
+        "along_the_run": r["along"],
         "launch": launch,
         "profiled_ms_per_step": rp["ms_per_step"],
         "kernels_ms": rp["kernels_ms"],
@@ -639,7 +678,7 @@ def main():
     }
     torch.cuda.empty_cache()
     if args.workload == "cfg2" and not variant and not args.no_active:
-        res["active_phase"] = active_phase(cfg, args.steps, args.warmup, args.profile_steps)
+        res["active_phase"] = active_phase(cfg, min(steps, ACTIVE_STEPS), args.warmup, args.profile_steps)
     if not args.no_batched:
         res["batched"] = batched_path(100, 5)
     if not args.no_surrogate:

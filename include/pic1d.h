@@ -319,22 +319,24 @@ typedef struct {
 
 /* Autotuner of the launch shape: times trial_steps real steps (at least one
  * sort cycle) for each candidate -- the particle kernel's tile shape (4, 8 or
- * 16 particles per lane; the deposit window, 128 or 64 cells for the TABLE
- * backend, 32 or 64 for OFF and EXACT, wherever that shape is built), push
+ * 16 particles per lane; the deposit window, 128 cells for the TABLE backend,
+ * 32 or 64 for OFF and EXACT, wherever that shape is built: never below the
+ * backend's default, which holds a tile's particles once a heated plasma spreads
+ * them between sorts), push
  * blocks per CU in {1,2,3,4,6,8}, the XCD-aware tile walk on/off, sort_interval
  * in {1,2,5,10,25,50,100}, then (when sorting) 8, 16 or 32 sort bins per cell
- * -- one knob at a time, and keeps the fastest; a tile
- * shape or block count other than the starting one must beat it again when the
- * two are timed alternately twice.  The trial steps advance the simulation; the
+ * -- one knob at a time, and keeps the fastest; a tile shape, block count or
+ * sort granularity other than the starting one must beat it again when the two
+ * are timed alternately twice.  The trial steps advance the simulation; the
  * physics does not depend on these choices (particle order and launch shape do
  * not change any result).  Errors: EINVAL, ESTATE, ECAPACITY, ENONFINITE. */
 int pic1d_autotune(pic1d_state* st, int32_t trial_steps, pic1d_tune_out* out);
 
 /* Set the particle kernel's launch shape directly: blocks per CU (1..32),
  * particles per lane of a tile (4, 8, 16) and the deposit window in cells (the
- * combinations pic1d_autotune lists; the MLP backend has 8 and 32 only).  The
- * results do not depend on it.  Errors: EINVAL (a shape that is not built),
- * ESTATE. */
+ * combinations pic1d_autotune lists, and a 64-cell window for the TABLE
+ * backend; the MLP backend has 8 and 32 only).  The results do not depend on
+ * it.  Errors: EINVAL (a shape that is not built), ESTATE. */
 int pic1d_set_push_shape(pic1d_state* st, int32_t blocks_per_cu, int32_t ppt, int32_t window);
 
 /* Granularity of the cell sort: after a sort every species' particles are in
