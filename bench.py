@@ -254,7 +254,7 @@ def timed_run(sim, steps, warmup, profile=True, chunk=None):
                 m0=m0, m1=m1)
 
 
-def pick_launch(sim, trial_steps=200, graph_steps=100):
+def pick_launch(sim, trial_steps=200, graph_steps=100, force=None):
     """Eager launches or replays of `graph_steps`-step HIP graphs, whichever runs
     the same steps faster here (the results are identical either way): time
     trial_steps real steps each way and keep the faster.  The graph trial first
@@ -265,9 +265,12 @@ def pick_launch(sim, trial_steps=200, graph_steps=100):
     sim.set_graph(graph_steps)
     graph = timed_run(sim, trial_steps, 2 * graph_steps, profile=False)["ms_per_step"]
     mode = "graph" if graph < eager else "eager"
+    if force:
+        mode = force
     sim.set_graph(graph_steps if mode == "graph" else 0)
     return {"mode": mode, "graph_steps": graph_steps if mode == "graph" else 0,
-            "trial_steps": trial_steps, "trial_ms_per_step": {"eager": eager, "graph": graph}}
+            "trial_steps": trial_steps, "trial_ms_per_step": {"eager": eager, "graph": graph},
+            **({"set_by_flag": True} if force else {})}
 
 
 def hbm_bytes_per_launch(r):
@@ -510,7 +513,7 @@ def cascade_run(chunks, chunk_steps, profile_steps, mlp_train_steps=0, fallback_
     return out
 
 
-def plain_path(cfg, steps, warmup, profile_steps, chunk=None, push_shape=None):
+def plain_path(cfg, steps, warmup, profile_steps, chunk=None, push_shape=None, launch_mode=None):
     """Autotune, pick eager or graph launches, time `steps` steps after `warmup`,
     then a profiled window of eager launches for the kernel breakdown.  With
     push_shape (blocks per CU, particles per lane, window), that tile shape replaces
@@ -525,7 +528,7 @@ def plain_path(cfg, steps, warmup, profile_steps, chunk=None, push_shape=None):
         tune = dict(tune, push_blocks_per_cu=push_shape[0], push_ppt=push_shape[1], deposit_window=push_shape[2],
                     shape_set_by_flag=True)
     print(f"# autotuned: {tune}", file=sys.stderr, flush=True)
-    launch = pick_launch(sim)
+    launch = pick_launch(sim, force=launch_mode)
     print(f"# launch: {launch}", file=sys.stderr, flush=True)
     r = timed_run(sim, steps, warmup, profile=False, chunk=chunk)
     # kernel breakdown and roofline: events around every launch, eager launches
@@ -585,6 +588,9 @@ def main():
                     help="mass-ratio variant: m_i/m_e instead of the workload's 100")
     ap.add_argument("--push-shape", default=None,
                     help="BPC,PPT,WINDOW: the particle kernel's tile shape instead of the tuner's (for counter runs)")
+    ap.add_argument("--launch", default=None, choices=["eager", "graph"],
+                    help="launch mode of the timed steps instead of the faster of the two trials "
+                         "(counter runs: eager)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -637,7 +643,8 @@ def main():
     # steps): long runs also report it per 2000 steps
     shape = tuple(int(x) for x in args.push_shape.split(",")) if args.push_shape else None
     r, rp, tune, launch = plain_path(cfg, steps, args.warmup, args.profile_steps,
-                                     chunk=2000 if steps >= 4000 else None, push_shape=shape)
+                                     chunk=2000 if steps >= 4000 else None, push_shape=shape,
+                                     launch_mode=args.launch)
     roof = push_roofline(rp)
     # HBM bytes per k_push launch (rocprofv3), measured on the unmodified workload only
     traffic = measured_traffic(args.backend, args.workload) if not variant else None
