@@ -4,7 +4,8 @@ surrogate-network path beside the table and exact paths, and the FP64 oracle
 timed on the host as a CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--backend table|exact|off]
-                    [--workload cfg2|cfg1] [--no-cpu-baseline] [--no-surrogate]
+                    [--workload cfg2|cfg1|cfg4] [--no-cpu-baseline] [--no-surrogate]
+                    [--push-shape BPC,PPT,WINDOW] [--launch eager|graph]
     python bench.py --copy-calibration     # plain 256 MiB device copy, for HBM counters
     python bench.py --cascade              # the combined cascade run (cfg5) on its own
 
