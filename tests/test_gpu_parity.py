@@ -181,6 +181,8 @@ def test_cfg2_full_size_sampled_parity_and_ledger():
     sim = _sim(cfg)
     tune = sim.autotune(trial_steps=10)
     _print("cfg2 autotune", tune)
+    assert tune["deposit_window"] == 128      # the tuner keeps TABLE's window at its default
+    assert tune["sort_granularity"] in (8, 16, 32)
     sim.step(5)
     m0 = sim.moments(0)
     before = parity.snapshot(sim)
